@@ -1,0 +1,172 @@
+"""Seeded synthetic uplink NOMA data for the APSM detector.
+
+This module draws the workload the detector is run on: channels, constellation
+symbols, transmitter nonlinearity, noise.  It holds none of the detector's own
+arithmetic (no real split, no kernels, no projections, no decisions); the same
+float32 arrays it returns are fed unchanged to the FP64 oracle and to the HIP
+library.
+
+Signal model: the non-dispersive uplink of Sec. II-C, eqn:uplink_signal,
+r(t) = sum_k sqrt(p_k) x_k(t) h_k + n(t), with x_k the (optionally Rapp
+PA-distorted) constellation symbol b_k(t) of user k.
+
+Storage convention for complex arrays handed to the library (an interface both
+sides must agree on):
+
+* a complex vector r in C^M is stored as M2 = 2M float32 values
+  [Re r_0 .. Re r_{M-1}, Im r_0 .. Im r_{M-1}];
+* a complex symbol b is stored as two float32 values (Re b, Im b);
+* a decided/true symbol is stored as one uint8 label
+  (gray(i_re) << bits_per_axis) | gray(i_im), with i_re / i_im the per-axis
+  level index in increasing amplitude order and gray the binary-reflected
+  Gray code of that index.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+# Per-axis amplitude levels of the unit-average-energy square constellations
+# (QPSK: +-1/sqrt2; 16-QAM: {+-1, +-3}/sqrt10), increasing order.
+_LEVELS = {
+    "qpsk": np.array([-1.0, 1.0]) / np.sqrt(2.0),
+    "qam16": np.array([-3.0, -1.0, 1.0, 3.0]) / np.sqrt(10.0),
+}
+BITS_PER_AXIS = {"qpsk": 1, "qam16": 2}
+
+
+def gray(i: np.ndarray) -> np.ndarray:
+    """Binary-reflected Gray code of a non-negative integer array."""
+    i = np.asarray(i)
+    return i ^ (i >> 1)
+
+
+def levels(modulation: str) -> np.ndarray:
+    return _LEVELS[modulation].copy()
+
+
+def label_of(idx_re: np.ndarray, idx_im: np.ndarray, modulation: str) -> np.ndarray:
+    b = BITS_PER_AXIS[modulation]
+    return ((gray(idx_re) << b) | gray(idx_im)).astype(np.uint8)
+
+
+@dataclass
+class InstanceSpec:
+    """Shape and channel recipe of one detector instance."""
+
+    K: int                      # users
+    M: int                      # receive antennas (complex); M2 = 2M reals
+    P: int                      # pilot (training) symbols per user
+    S: int                      # data symbols per user
+    snr_db: float               # per-antenna SNR relative to a unit-power user
+    modulation: str = "qpsk"    # "qpsk" | "qam16"
+    near_far_db: Optional[tuple] = None   # (lo, hi): p_k = 10^(U[lo,hi]/10)
+    rapp: Optional[tuple] = None          # (p, A_sat) Rapp AM/AM at each transmitter
+    seed: int = 0
+
+
+@dataclass
+class Instance:
+    spec: InstanceSpec
+    rx_pilot: np.ndarray        # [P][2M] float32
+    sym_pilot: np.ndarray       # [P][K][2] float32 (Re, Im) of the transmitted symbol b
+    rx_data: np.ndarray         # [S][2M] float32
+    sym_data: np.ndarray        # [S][K][2] float32
+    truth: np.ndarray           # [S][K] uint8 labels of the data symbols
+    scale: float                # real scalar applied to every received vector
+    extras: dict = field(default_factory=dict)
+
+
+def _draw_symbols(rng: np.random.Generator, n: int, K: int, modulation: str):
+    L = len(_LEVELS[modulation])
+    idx = rng.integers(0, L, size=(n, K, 2))
+    lv = _LEVELS[modulation]
+    b = lv[idx[..., 0]] + 1j * lv[idx[..., 1]]
+    return b, idx
+
+
+def _rapp(b: np.ndarray, p: float, a_sat: float) -> np.ndarray:
+    """Rapp solid-state PA AM/AM characteristic (no AM/PM)."""
+    a = np.abs(b)
+    return b * (1.0 + (a / a_sat) ** (2.0 * p)) ** (-1.0 / (2.0 * p))
+
+
+def _to_planar(r: np.ndarray) -> np.ndarray:
+    return np.concatenate([r.real, r.imag], axis=-1).astype(np.float32)
+
+
+def make_instance(spec: InstanceSpec) -> Instance:
+    """Draw one instance.  Every random number comes from PCG64(spec.seed) in a
+    fixed order, so the same spec gives byte-identical arrays."""
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    K, M = spec.K, spec.M
+    # Block-fading i.i.d. Rayleigh channel, H[m, k] ~ CN(0, 1).
+    H = (rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))) / np.sqrt(2.0)
+    if spec.near_far_db is not None:
+        lo, hi = spec.near_far_db
+        p = 10.0 ** (rng.uniform(lo, hi, size=K) / 10.0)
+    else:
+        p = np.ones(K)
+    n0 = 10.0 ** (-spec.snr_db / 10.0)
+
+    def block(n):
+        b, idx = _draw_symbols(rng, n, K, spec.modulation)
+        x = _rapp(b, *spec.rapp) if spec.rapp is not None else b
+        noise = (rng.standard_normal((n, M)) + 1j * rng.standard_normal((n, M))) * np.sqrt(n0 / 2.0)
+        r = (x * np.sqrt(p)[None, :]) @ H.T + noise
+        return r, b, idx
+
+    r_p, b_p, _ = block(spec.P)
+    r_d, b_d, idx_d = block(spec.S)
+    # One real scale per instance so that the pilot block has unit mean
+    # squared norm; the same scale applies to the data block.
+    scale = 1.0 / np.sqrt(np.mean(np.sum(np.abs(r_p) ** 2, axis=1)))
+    r_p = r_p * scale
+    r_d = r_d * scale
+
+    sym_p = np.stack([b_p.real, b_p.imag], axis=-1).astype(np.float32)
+    sym_d = np.stack([b_d.real, b_d.imag], axis=-1).astype(np.float32)
+    truth = label_of(idx_d[..., 0], idx_d[..., 1], spec.modulation)
+    return Instance(spec=spec, rx_pilot=_to_planar(r_p), sym_pilot=sym_p,
+                    rx_data=_to_planar(r_d), sym_data=sym_d, truth=truth,
+                    scale=float(scale), extras={"H": H, "p": p})
+
+
+def planar_to_complex(x: np.ndarray) -> np.ndarray:
+    """Inverse of the storage convention: [..., 2M] float -> [..., M] complex128."""
+    x = np.asarray(x, dtype=np.float64)
+    M = x.shape[-1] // 2
+    return x[..., :M] + 1j * x[..., M:]
+
+
+def pair_to_complex(x: np.ndarray) -> np.ndarray:
+    """[..., 2] (Re, Im) float -> [...] complex128."""
+    x = np.asarray(x, dtype=np.float64)
+    return x[..., 0] + 1j * x[..., 1]
+
+
+# Named workloads.  Sizes follow the five benchmark configurations of the
+# detector (tiny plain case, realistic slot, batched mixed shapes, differentiable
+# unrolled training, large array) plus the paper's own shape (Sec. V: 6 users,
+# 16 antennas, 685 training and 3840 data symbols, W = 20, sigma^2 = 0.05).
+BASE_SEED = 220105024
+
+
+def spec_plain_small(seed: int = BASE_SEED + 1, S: int = 2048) -> InstanceSpec:
+    return InstanceSpec(K=4, M=8, P=256, S=S, snr_db=10.0, modulation="qpsk", seed=seed)
+
+
+SLOT_SNRS_DB = (5.0, 10.0, 15.0, 20.0)
+
+
+def spec_slot(snr_db: float, seed: int = BASE_SEED + 2, S: int = 1 << 20,
+              P: int = 1024) -> InstanceSpec:
+    return InstanceSpec(K=6, M=16, P=P, S=S, snr_db=snr_db, modulation="qpsk",
+                        near_far_db=(-6.0, 0.0), rapp=(2.0, 1.0),
+                        seed=seed + int(round(snr_db * 10)))
+
+
+def spec_paper_shape(seed: int = BASE_SEED + 6) -> InstanceSpec:
+    return InstanceSpec(K=6, M=16, P=685, S=3840, snr_db=20.0, modulation="qpsk", seed=seed)
