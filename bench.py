@@ -1,0 +1,237 @@
+"""Benchmark of the APSM detector hot path on one MI355X.
+
+One step = the whole path on one realistic slot at four SNR points
+(5, 10, 15, 20 dB): for each point, training on 1024 pilot symbols
+(2048 real steps, window 32, dictionary cap 1024) followed by detection,
+decisions and symbol-error counting on 1,048,576 data symbols of 6 users
+received on 16 antennas (near-far powers in [-6, 0] dB, Rapp PA p = 2,
+A_sat = 1).  Inputs are synthetic (seeded) and resident in HBM before the
+timed region starts.  The four trainings run on their own streams (one
+workgroup each), the detections on the main stream.
+
+Prints one JSON line: whole-step throughput in detected user-symbols/s, the
+roofline of the detection kernel (its average duration measured with HIP
+events on its stream), and the FP64 oracle timed on a bounded sample of the
+same workload on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = ("detected symbols/s and kernel evals/s vs roofline at oracle SER; "
+          "batched vs plain")
+PEAK_FP32_MFMA_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(spec_fn, snr, params, S_full, n_inst):
+    """Time the FP64 oracle on a bounded sample: full training of one instance
+    plus detection of 1024 data symbols, extrapolated linearly to one step."""
+    import oracle as O
+    import synth
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    inst = synth.make_instance(spec_fn(snr, S=1024))
+    p = O.APSMParams(sigma2=params.sigma2, eps=params.eps, mu=params.mu, window=params.window,
+                     w_lin=params.w_lin, w_gauss=params.w_gauss, dict_cap=params.dict_cap)
+    t0 = time.perf_counter()
+    f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, p)
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    soft = O.detect_planar(f, inst.rx_data)
+    O.symbol_errors(O.decide(soft, "qpsk"), inst.truth)
+    t_det = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.restore_original_limits()
+    K = inst.spec.K
+    t_step = n_inst * (t_train + t_det * S_full / 1024)
+    return {
+        "value": n_inst * S_full * K / t_step,
+        "unit": "user-symbols/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle, 1 thread: full training of one {snr:g} dB instance "
+                   f"({t_train:.2f} s) and detection of 1024 of {S_full} data symbols "
+                   f"({t_det:.2f} s), extrapolated linearly to {n_inst} instances x {S_full} symbols"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the detector has no multi-GPU path to measure.", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    import paper_2201_05024_amd as A
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    A.library()  # fail loudly if the HIP library is missing
+
+    snrs = synth.SLOT_SNRS_DB
+    params = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, w_lin=0.5, w_gauss=0.5,
+                      dict_cap=1024)
+    log(f"[bench] generating {len(snrs)} slot instances")
+    insts = [synth.make_instance(synth.spec_slot(s)) for s in snrs]
+    K, M2, P, S = insts[0].spec.K, 2 * insts[0].spec.M, insts[0].spec.P, insts[0].spec.S
+    rx_p = [torch.from_numpy(i.rx_pilot).to(dev) for i in insts]
+    sym_p = [torch.from_numpy(i.sym_pilot).to(dev) for i in insts]
+    rx_d = [torch.from_numpy(i.rx_data).to(dev) for i in insts]
+    truth = [torch.from_numpy(i.truth).to(dev) for i in insts]
+    models = [A.Model(M2, K, params.dict_cap, dev, params.sigma2) for _ in insts]
+    soft = [torch.empty((S, K, 2), dtype=torch.float32, device=dev) for _ in insts]
+    hard = [torch.empty((S, K), dtype=torch.uint8, device=dev) for _ in insts]
+    errs = [torch.zeros(K, dtype=torch.int64, device=dev) for _ in insts]
+    main_s = torch.cuda.current_stream()
+    side = [torch.cuda.Stream() for _ in insts]
+    torch.cuda.synchronize()
+
+    det_events = []
+
+    def step(record):
+        start = torch.cuda.Event()
+        start.record(main_s)
+        for i, s in enumerate(side):
+            s.wait_event(start)
+            with torch.cuda.stream(s):
+                A.train(rx_p[i], sym_p[i], params, model=models[i], stream=s)
+            done = torch.cuda.Event()
+            done.record(s)
+            main_s.wait_event(done)
+        for e in errs:
+            e.zero_()
+        for i in range(len(insts)):
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(main_s)
+            A.detect(models[i], rx_d[i], modulation="qpsk", truth=truth[i], soft=soft[i],
+                     hard=hard[i], errors=errs[i], stream=main_s)
+            if record:
+                e1.record(main_s)
+                det_events.append((e0, e1))
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+
+    # training alone, for the report
+    t_ev0, t_ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_ev0.record(main_s)
+    A.train(rx_p[0], sym_p[0], params, model=models[0], stream=main_s)
+    t_ev1.record(main_s)
+    torch.cuda.synchronize()
+    train_ms = t_ev0.elapsed_time(t_ev1)
+
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log("[bench] timed region done")
+
+    det_ms = [a.elapsed_time(b) for a, b in det_events]
+    det_avg_s = float(np.mean(det_ms)) / 1e3
+    n_inst = len(insts)
+    sym_per_step = n_inst * S * K
+    value = sym_per_step * args.steps / elapsed
+    D = params.dict_cap
+    S_r = 2 * S
+    evals_per_launch = S_r * D
+    flops_per_launch = evals_per_launch * 2 * M2       # the sample x dictionary inner products
+    achieved_tflops = flops_per_launch / det_avg_s / 1e12
+    ser = {f"{s:g}dB": float(e.sum().item()) / (S * K) for s, e in zip(snrs, errs)}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "user-symbols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Rayleigh channel, near-far, Rapp PA, AWGN)",
+        "config": {
+            "workload": ("realistic slot: K=6 users QPSK, 16 Rx antennas (2M=32), near-far "
+                         "[-6,0] dB, Rapp PA p=2 A_sat=1, SNR 5/10/15/20 dB (4 instances), "
+                         "1024 pilots, 1048576 data symbols, W=32, sigma2=0.5, eps=0.05, "
+                         "mu=1, dictionary cap 1024"),
+            "instances_per_step": n_inst,
+            "data_symbols": S,
+            "pilots": P,
+        },
+        "roofline": {
+            "kernel": "detect_kernel<32,6,2>",
+            "bound": "mfma",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS,
+            "traffic": None,
+            "per_launch": {"real_vectors": S_r, "dictionary": D,
+                           "flops_counted": flops_per_launch,
+                           "avg_ms": det_avg_s * 1e3, "launches_timed": len(det_ms)},
+        },
+        "detect_only": {
+            "user_symbols_per_s": S * K / det_avg_s,
+            "kernel_evals_per_s": evals_per_launch / det_avg_s,
+        },
+        "train_ms_per_instance": train_ms,
+        "train_steps_per_instance": 2 * P,
+        "ser_gpu": ser,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(lambda snr, S: synth.spec_slot(snr, S=S), 10.0, params,
+                                           S, n_inst)
+    if args.copy_calibration:
+        n = 64 << 20
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,164 @@
+/*
+ * apsm.h - C ABI of the MI355X (gfx950) APSM partially linear multiuser
+ * detector library (libapsm.so).
+ *
+ * The method is the one of Mehlhose et al., "GPU-accelerated partially linear
+ * multiuser detection for 5G and beyond URLLC systems" (arXiv 2201.05024):
+ * per user k a real filter f_k in the sum RKHS H = H_L + H_G (Sec. II-B,
+ * Fact 1),
+ *
+ *     f_k(x) = w_k^T x + sum_i alpha[i][k] * exp(-||x - d_i||^2 / (2 sigma^2)),
+ *
+ * trained by windowed parallel hyperslab projections (Sec. II-D, eqn:apsm,
+ * eqn:beta) and evaluated on every received vector for detection (Sec. III-B)
+ * with g_k(r) = f_k(r1) + i f_k(r2) (Sec. II-D real split).
+ *
+ * Conventions shared by every entry point:
+ *  - Array pointers are DEVICE pointers unless the comment says HOST.
+ *  - A complex vector r in C^M is stored as M2 = 2M float32 values
+ *    [Re r_0 .. Re r_{M-1}, Im r_0 .. Im r_{M-1}] (this is r1 of Sec. II-D;
+ *    r2 = [Im r; -Re r] is formed inside the kernels and never stored).
+ *  - A complex symbol is stored as two float32 values (Re, Im).
+ *  - A decided symbol is one uint8 label (gray(i_re) << b) | gray(i_im), b the
+ *    bits per axis (1 for QPSK, 2 for 16-QAM), i_re / i_im the per-axis level
+ *    index in increasing amplitude order, gray the binary-reflected Gray code.
+ *    Constellations have unit average energy: QPSK levels +-1/sqrt2, 16-QAM
+ *    levels {-3,-1,1,3}/sqrt10; a value exactly on a threshold takes the
+ *    higher level.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL is the null stream).  Arguments are validated on the host before
+ *    anything is launched: a call that returns an error launched nothing.
+ *  - The caller allocates and owns every device buffer.  The library never
+ *    allocates device memory.
+ *  - No C++ exception crosses this interface.  Calls on different streams are
+ *    independent; calls that write the same buffers must be ordered by the
+ *    caller.
+ */
+#ifndef APSM_H
+#define APSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define APSM_OK                 0
+#define APSM_ERR_INVALID_ARG    1  /* null pointer, non-finite or out-of-range parameter */
+#define APSM_ERR_SHAPE          2  /* sizes inconsistent with each other or the model    */
+#define APSM_ERR_UNSUPPORTED    3  /* valid but beyond this build's limits (see below)   */
+#define APSM_ERR_HIP            4  /* a HIP launch failed; see apsm_last_hip_error()     */
+
+/* ---- limits of this build ------------------------------------------- */
+#define APSM_MAX_M2       128      /* real input dimension 2M                       */
+#define APSM_MAX_K        16       /* users per instance                            */
+#define APSM_MAX_WINDOW   64       /* sliding-window size W                         */
+#define APSM_MAX_DICT     65536    /* dictionary capacity                           */
+
+/* Modulations for apsm_detect: the value is the number of bits per symbol. */
+#define APSM_MOD_NONE   0          /* no decisions, soft outputs only               */
+#define APSM_MOD_QPSK   2
+#define APSM_MOD_QAM16  4
+
+/* Design parameters of the iteration (HOST struct).
+ *  sigma2      Gaussian kernel width sigma^2 > 0 (Sec. II-A).
+ *  eps         hyperslab half-width eps >= 0 (eqn:convex_set).
+ *  mu          relaxation in (0, 2): f_{n+1} = f_n + mu * sum_j q_j beta_j kappa(r_j, .);
+ *              mu = 1 is exactly eqn:apsm (the q_j sum to one).
+ *  w_lin,
+ *  w_gauss     weights of the sum space (Sec. II-B), >= 0 and not both 0.
+ *  window      W >= 1: J_n = {n-W+1..n} for n >= W-1, else {0..n}.
+ *  dict_cap    capacity of the Gaussian dictionary, >= window.  Sample r_n
+ *              enters the dictionary at the start of step n; when it is full
+ *              the oldest Gaussian term is dropped first (its linear part
+ *              stays).  dict_cap >= 2P gives the paper's ever-growing
+ *              dictionary exactly.
+ *  pos_weights HOST pointer to `window` positive floats omega (omega[0] for the
+ *              newest set j = n), q_j = omega[n-j] / sum_{i in J_n} omega[n-i];
+ *              NULL for uniform q_j = 1/|J_n| (eqn:apsm's weights, Sec. II-D). */
+typedef struct apsm_params {
+  float sigma2;
+  float eps;
+  float mu;
+  float w_lin;
+  float w_gauss;
+  int32_t window;
+  int32_t dict_cap;
+  int32_t reserved;           /* must be 0 */
+  const float* pos_weights;
+} apsm_params_t;
+
+/* A trained detector: the whole filter state (Sec. III-B: dictionary plus
+ * coefficients).  HOST struct of DEVICE pointers, all caller-allocated.
+ *  dict   [dict_cap][M2]  Gaussian dictionary ring; slot of sample n is n % dict_cap;
+ *                         unused slots hold zeros.
+ *  alpha  [dict_cap][K]   Gaussian coefficients (wG * gamma_i of Sec. II-D); zero for
+ *                         unused slots.
+ *  w      [K][M2]         linear coefficients (wL * gamma^(L) of Sec. II-D).
+ *  state  int32[4]        written by training: {entries in use, next slot,
+ *                         training steps done, status flags}; flag bit 0 =
+ *                         non-finite training input seen.
+ * sigma2 travels with the call (apsm_detect) rather than in this struct. */
+typedef struct apsm_model {
+  int32_t M2;
+  int32_t K;
+  int32_t dict_cap;
+  int32_t reserved;           /* must be 0 */
+  float* dict;
+  float* alpha;
+  float* w;
+  int32_t* state;
+} apsm_model_t;
+
+/* Training (Sec. II-D eqn:apsm with eqn:beta; Sec. III-B training phase).
+ * Resets `model` to f_0 = 0 and runs the 2P steps n = 0..2P-1 of the real
+ * training sequence r_{2t} = r1(t), r_{2t+1} = r2(t), b_{k,2t} = Re b_k(t),
+ * b_{k,2t+1} = Im b_k(t).
+ *  params     HOST, see apsm_params_t.
+ *  M2         2M, even, 2..APSM_MAX_M2;  K  1..APSM_MAX_K;  P >= 1 pilots.
+ *  rx_pilot   [P][M2] received pilot vectors (r1 layout).
+ *  sym_pilot  [P][K][2] transmitted pilot symbols (Re, Im).
+ *  model      HOST struct; model->M2, K, dict_cap must equal M2, K,
+ *             params->dict_cap.
+ * Returns APSM_OK or an error code; the filter is ready once the stream
+ * reaches the launch. */
+int apsm_train(const apsm_params_t* params, int M2, int K, int P,
+               const float* rx_pilot, const float* sym_pilot,
+               const apsm_model_t* model, void* stream);
+
+/* Detection (Sec. III-B): for every received vector r(s), s = 0..S-1,
+ * g_k = f_k(r1) + i f_k(r2) with the frozen filter `model` (read only).
+ *  model      HOST struct of a trained model.
+ *  sigma2     the kernel width the model was trained with (> 0).
+ *  S          number of received vectors, >= 0 (0 launches nothing).
+ *  rx         [S][M2] received vectors (r1 layout).
+ *  soft       [S][K][2] (Re g_k, Im g_k) output, or NULL.
+ *  hard       [S][K] uint8 labels output, or NULL; needs modulation != NONE.
+ *  modulation APSM_MOD_NONE / APSM_MOD_QPSK / APSM_MOD_QAM16.
+ *  truth      [S][K] uint8 transmitted labels, or NULL.
+ *  err_count  [K] int64: the number of s with decided label != truth[s][k]
+ *             is ADDED to err_count[k] (zero it first); NULL if truth is NULL.
+ * At least one of soft / hard / err_count must be non-NULL. */
+int apsm_detect(const apsm_model_t* model, float sigma2, int S,
+                const float* rx, float* soft, uint8_t* hard, int modulation,
+                const uint8_t* truth, int64_t* err_count, void* stream);
+
+/* Synchronous copy of model->state into host_state[4]; waits for all work on
+ * the device. */
+int apsm_get_status(const apsm_model_t* model, int32_t* host_state);
+
+/* Static description of an error code; never NULL. */
+const char* apsm_strerror(int code);
+
+/* Text of the last HIP error seen by this thread's calls ("" if none). */
+const char* apsm_last_hip_error(void);
+
+/* Library version, e.g. "0.1.0". */
+const char* apsm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APSM_H */

@@ -1,0 +1,203 @@
+"""APSM partially linear multiuser detection on MI355X (gfx950).
+
+A thin Python binding over libapsm.so (the C ABI declared in include/apsm.h):
+argument marshalling only.  Every step of training and detection runs in the
+library's HIP kernels; PyTorch provides device memory and the stream.  There
+is no CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+__all__ = ["Params", "Model", "train", "detect", "APSMError", "library", "LIB_PATH",
+           "MOD_NONE", "MOD_QPSK", "MOD_QAM16"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapsm.so")
+
+MOD_NONE, MOD_QPSK, MOD_QAM16 = 0, 2, 4
+_MODS = {None: MOD_NONE, "none": MOD_NONE, "qpsk": MOD_QPSK, "qam16": MOD_QAM16,
+         MOD_NONE: MOD_NONE, MOD_QPSK: MOD_QPSK, MOD_QAM16: MOD_QAM16}
+
+
+class APSMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = f"{where}: {library().apsm_strerror(code).decode()} (code {code})"
+        if code == 4:
+            msg += f": {library().apsm_last_hip_error().decode()}"
+        super().__init__(msg)
+        self.code = code
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [("sigma2", ctypes.c_float), ("eps", ctypes.c_float), ("mu", ctypes.c_float),
+                ("w_lin", ctypes.c_float), ("w_gauss", ctypes.c_float),
+                ("window", ctypes.c_int32), ("dict_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("pos_weights", ctypes.POINTER(ctypes.c_float))]
+
+
+class _CModel(ctypes.Structure):
+    _fields_ = [("M2", ctypes.c_int32), ("K", ctypes.c_int32), ("dict_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("dict", ctypes.c_void_p),
+                ("alpha", ctypes.c_void_p), ("w", ctypes.c_void_p), ("state", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libapsm.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2201_05024_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+        L.apsm_train.argtypes = [ctypes.POINTER(_CParams), i32, i32, i32, vp, vp,
+                                 ctypes.POINTER(_CModel), vp]
+        L.apsm_train.restype = i32
+        L.apsm_detect.argtypes = [ctypes.POINTER(_CModel), f32, i32, vp, vp, vp, i32, vp, vp, vp]
+        L.apsm_detect.restype = i32
+        L.apsm_get_status.argtypes = [ctypes.POINTER(_CModel), ctypes.POINTER(ctypes.c_int32)]
+        L.apsm_get_status.restype = i32
+        L.apsm_strerror.argtypes = [i32]
+        L.apsm_strerror.restype = ctypes.c_char_p
+        L.apsm_last_hip_error.argtypes = []
+        L.apsm_last_hip_error.restype = ctypes.c_char_p
+        L.apsm_version.argtypes = []
+        L.apsm_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Params:
+    """Design parameters (see apsm_params_t): sigma^2, eps, relaxation mu,
+    window W, sum-space weights, dictionary capacity, optional position
+    weights omega (omega[0] for the newest set)."""
+
+    sigma2: float = 0.5
+    eps: float = 0.05
+    mu: float = 1.0
+    window: int = 16
+    w_lin: float = 0.5
+    w_gauss: float = 0.5
+    dict_cap: int = 256
+    pos_weights: Optional[Sequence[float]] = None
+
+    def _c(self):
+        pw = None
+        keep = None
+        if self.pos_weights is not None:
+            keep = (ctypes.c_float * len(self.pos_weights))(*[float(x) for x in self.pos_weights])
+            pw = ctypes.cast(keep, ctypes.POINTER(ctypes.c_float))
+        p = _CParams(self.sigma2, self.eps, self.mu, self.w_lin, self.w_gauss,
+                     int(self.window), int(self.dict_cap), 0, pw)
+        return p, keep
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Model:
+    """A trained detector (the whole filter state) in caller-owned tensors."""
+
+    def __init__(self, M2: int, K: int, dict_cap: int, device=None, sigma2: float = 0.5):
+        torch = _torch()
+        dev = device if device is not None else torch.device("cuda")
+        self.M2, self.K, self.dict_cap, self.sigma2 = int(M2), int(K), int(dict_cap), float(sigma2)
+        self.dict = torch.zeros((dict_cap, M2), dtype=torch.float32, device=dev)
+        self.alpha = torch.zeros((dict_cap, K), dtype=torch.float32, device=dev)
+        self.w = torch.zeros((K, M2), dtype=torch.float32, device=dev)
+        self.state = torch.zeros(4, dtype=torch.int32, device=dev)
+
+    def _c(self) -> _CModel:
+        return _CModel(self.M2, self.K, self.dict_cap, 0, self.dict.data_ptr(),
+                       self.alpha.data_ptr(), self.w.data_ptr(), self.state.data_ptr())
+
+    def status(self):
+        out = (ctypes.c_int32 * 4)()
+        m = self._c()
+        rc = library().apsm_get_status(ctypes.byref(m), out)
+        if rc:
+            raise APSMError(rc, "apsm_get_status")
+        return {"size": out[0], "head": out[1], "steps": out[2], "flags": out[3]}
+
+
+def train(rx_pilot, sym_pilot, params: Params, model: Optional[Model] = None, stream=None) -> Model:
+    """rx_pilot [P][M2] float32, sym_pilot [P][K][2] float32 (device) -> Model."""
+    torch = _torch()
+    P, M2 = rx_pilot.shape
+    K = sym_pilot.shape[1]
+    _check(rx_pilot, torch.float32, (P, M2), "rx_pilot")
+    _check(sym_pilot, torch.float32, (P, K, 2), "sym_pilot")
+    if model is None:
+        model = Model(M2, K, params.dict_cap, rx_pilot.device, params.sigma2)
+    model.sigma2 = float(params.sigma2)
+    p, keep = params._c()
+    m = model._c()
+    rc = library().apsm_train(ctypes.byref(p), M2, K, P, rx_pilot.data_ptr(), sym_pilot.data_ptr(),
+                              ctypes.byref(m), _stream_handle(stream))
+    del keep
+    if rc:
+        raise APSMError(rc, "apsm_train")
+    return model
+
+
+def detect(model: Model, rx, modulation="qpsk", truth=None, want_soft: bool = True,
+           want_hard: bool = True, sigma2: Optional[float] = None, soft=None, hard=None,
+           errors=None, stream=None):
+    """Evaluate the frozen filter on rx [S][M2] float32.  Returns a dict with
+    'soft' [S][K][2] float32, 'hard' [S][K] uint8 and 'errors' [K] int64 (each
+    present when requested).  Output tensors may be passed in to reuse them;
+    `errors` is accumulated into, as the C ABI specifies."""
+    torch = _torch()
+    S = rx.shape[0]
+    _check(rx, torch.float32, (S, model.M2), "rx")
+    mod = _MODS[modulation]
+    dev = rx.device
+    if want_soft and soft is None:
+        soft = torch.empty((S, model.K, 2), dtype=torch.float32, device=dev)
+    if mod != MOD_NONE and want_hard and hard is None:
+        hard = torch.empty((S, model.K), dtype=torch.uint8, device=dev)
+    if truth is not None:
+        _check(truth, torch.uint8, (S, model.K), "truth")
+        if errors is None:
+            errors = torch.zeros(model.K, dtype=torch.int64, device=dev)
+    if soft is not None:
+        _check(soft, torch.float32, (S, model.K, 2), "soft")
+    if hard is not None:
+        _check(hard, torch.uint8, (S, model.K), "hard")
+    if errors is not None:
+        _check(errors, torch.int64, (model.K,), "errors")
+    m = model._c()
+    ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+    rc = library().apsm_detect(ctypes.byref(m), float(sigma2 if sigma2 is not None else model.sigma2),
+                               S, rx.data_ptr(), ptr(soft), ptr(hard), mod, ptr(truth),
+                               ptr(errors), _stream_handle(stream))
+    if rc:
+        raise APSMError(rc, "apsm_detect")
+    return {"soft": soft, "hard": hard, "errors": errors}

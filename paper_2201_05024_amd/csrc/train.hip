@@ -1,0 +1,413 @@
+// APSM training kernel for gfx950: windowed parallel hyperslab projections
+// (Sec. II-D, eqn:apsm, eqn:beta) over the real training sequence
+// r_{2t} = r1(t), r_{2t+1} = r2(t) of the pilot block.
+//
+// One workgroup trains one detector; the n-loop runs on the device.  Training
+// is serial in n, so the design goal is a short critical path per step with
+// two workgroup barriers:
+//
+//   A  every thread: append r_n to the dictionary ring (FIFO eviction), the
+//      kernel row kappa_G(r_n, d_i) over its own dictionary slots, the
+//      alpha-weighted partial sums of f_n(r_n), the new row/column of the
+//      window Gram matrix K(r_j, r_i) = wL r_j.r_i + wG kappa_G(r_j, r_i),
+//      and the kernel values of r_n against the dictionary entries that will
+//      be evicted while r_n is still in the window.
+//   -- barrier --
+//   C  one thread per (window member j, user k): f_n(r_j) (new member: the
+//      reduced partial sums plus w_k.r_n; old members: their running value
+//      minus the evicted Gaussian term), beta from eqn:beta, c = mu q_j beta.
+//   -- barrier --
+//   D  running predictions e_i += sum_j c_j K(r_j, r_i) for the members that
+//      stay, alpha[slot(j)] += c_j wG (slot owners), w_k += wL sum_j c_j r_j.
+//
+// The window predictions are thus updated incrementally (D Gaussian
+// evaluations per step instead of |J_n| * D); this is exact up to rounding
+// because every change of f is a finite sum of kernel sections whose values
+// at the window members are known.  All W projections use the same f_n, as
+// eqn:apsm requires.
+//
+// Dictionary slots are owned round-robin by the threads (slot s by thread
+// s % 256).  When cap * M2 fits, each thread keeps its slots' vectors and
+// coefficients in registers; otherwise they live in the model buffers.
+#include "apsm_internal.h"
+
+namespace apsm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// Sum over the 64 lanes of a wave; the result is valid in lane 63.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
+__device__ __forceinline__ float soft_threshold(float x, float eps) {
+  float m = fabsf(x) - eps;
+  return m > 0.0f ? copysignf(m, x) : 0.0f;
+}
+
+// Shared-memory layout, sized at launch from W, K and M2P.
+struct Lds {
+  float* gram;   // [R][R], R = W + 1 (ring over window members)
+  float* evkr;   // [W][W-1] kappa_G(r_j, d_v) for the entries v evicted while j is in the window
+  float* e;      // [W][KP] running predictions f(r_j)
+  float* c;      // [W][KP] mu q_j beta_jk of the current step
+  float* nrm;    // [W] ||r_j||^2
+  float* rwin;   // [R][M2P] window members' vectors
+  float* wlin;   // [KP][M2P] linear coefficients
+  float* part;   // [kWaves][KP] per-wave partial sums of the Gaussian part of f_n(r_n)
+  float* aev;    // [KP] coefficients of the evicted entry
+  float* qden;   // [W+1] prefix sums of omega
+};
+
+__host__ __device__ inline size_t lds_floats(int W, int KP, int M2P) {
+  int R = W + 1;
+  return (size_t)R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 2 * (size_t)W * KP + W +
+         (size_t)R * M2P + (size_t)KP * M2P + kWaves * KP + KP + (W + 1);
+}
+
+__device__ inline Lds carve(float* base, int W, int KP, int M2P) {
+  Lds s;
+  int R = W + 1;
+  float* p = base;
+  s.gram = p; p += R * R;
+  s.evkr = p; p += W * (W > 1 ? W - 1 : 1);
+  s.e = p; p += W * KP;
+  s.c = p; p += W * KP;
+  s.nrm = p; p += W;
+  s.rwin = p; p += R * M2P;
+  s.wlin = p; p += KP * M2P;
+  s.part = p; p += kWaves * KP;
+  s.aev = p; p += KP;
+  s.qden = p;
+  return s;
+}
+
+// Component m of r_n (zero in the padding m >= M2).
+__device__ __forceinline__ float sample_comp(const float* rx, int M2, int M, int n, int m) {
+  if (m >= M2) return 0.0f;
+  const float* src = rx + (size_t)(n >> 1) * M2;
+  if ((n & 1) == 0) return src[m];
+  return m < M ? src[m + M] : -src[m - M];
+}
+
+template <int M2P, int KP, int SLOTS>
+__global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
+  extern __shared__ float lds_raw[];
+  const int tid = threadIdx.x;
+  const int W = a.W, R = W + 1, cap = a.cap, K = a.K, M2 = a.M2, M = a.M;
+  const int T = 2 * a.P;
+  const int EVS = W > 1 ? W - 1 : 1;
+  Lds s = carve(lds_raw, W, KP, M2P);
+
+  for (int i = tid; i < KP * M2P; i += kThreads) s.wlin[i] = 0.0f;
+  for (int i = tid; i < W * KP; i += kThreads) { s.e[i] = 0.0f; s.c[i] = 0.0f; }
+  if (tid == 0) {
+    float acc = 0.0f;
+    s.qden[0] = 0.0f;
+    for (int p = 0; p < W; ++p) { acc += a.omega[p]; s.qden[p + 1] = acc; }
+  }
+
+  // Register-resident slots (SLOTS > 0): slot tid + kThreads * u.
+  float dreg[SLOTS > 0 ? SLOTS : 1][M2P];
+  float dnorm[SLOTS > 0 ? SLOTS : 1];
+  float areg[SLOTS > 0 ? SLOTS : 1][KP];
+  if constexpr (SLOTS > 0) {
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      dnorm[u] = 0.0f;
+#pragma unroll
+      for (int m = 0; m < M2P; ++m) dreg[u][m] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
+    }
+  } else {
+    // Model buffers hold the dictionary; start from an empty one.
+    for (size_t i = tid; i < (size_t)cap * K; i += kThreads) a.alpha[i] = 0.0f;
+  }
+  __shared__ int block_flags;
+  if (tid == 0) block_flags = 0;
+  int flags = 0;
+  __syncthreads();
+
+  for (int n = 0; n < T; ++n) {
+    // ------------------------------------------------------------ phase A
+    // r_n is kept in registers by the register path; the model-buffer path
+    // re-reads its components (L1 hits) to stay clear of large arrays.
+    float rn[SLOTS > 0 ? M2P : 1];
+    float nn = 0.0f;
+    if constexpr (SLOTS > 0) {
+#pragma unroll
+      for (int m = 0; m < M2P; ++m) {
+        rn[m] = sample_comp(a.rx, M2, M, n, m);
+        nn = fmaf(rn[m], rn[m], nn);
+      }
+    } else {
+      for (int m = 0; m < M2; ++m) {
+        const float v = sample_comp(a.rx, M2, M, n, m);
+        nn = fmaf(v, v, nn);
+      }
+    }
+    const int sn = n % cap;                 // slot of r_n
+    const bool evicting = n >= cap;
+    const int nmod_r = n % R, nmod_w = n % W;
+    const int jlo = n - W + 1;              // window members have index >= jlo
+    const int evlo = n - cap + 1;           // oldest entry in the dictionary after the append
+    if (tid < M2P) s.rwin[nmod_r * M2P + tid] = sample_comp(a.rx, M2, M, n, tid);
+    if (tid == 0) s.nrm[nmod_w] = nn;
+
+    float part[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) part[k] = 0.0f;
+
+    if constexpr (SLOTS > 0) {
+#pragma unroll
+      for (int u = 0; u < SLOTS; ++u) {
+        const int slot = tid + kThreads * u;
+        if (slot == sn) {                    // append (and evict)
+          if (evicting) {
+#pragma unroll
+            for (int k = 0; k < KP; ++k) s.aev[k] = areg[u][k];
+          }
+#pragma unroll
+          for (int m = 0; m < M2P; ++m) dreg[u][m] = rn[m];
+          dnorm[u] = nn;
+#pragma unroll
+          for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
+        }
+        if (slot < cap && slot <= n) {
+          int back = sn - slot;
+          if (back < 0) back += cap;
+          const int idx = n - back;         // training index held by this slot
+          float dot = 0.0f;
+#pragma unroll
+          for (int m = 0; m < M2P; ++m) dot = fmaf(rn[m], dreg[u][m], dot);
+          const float kg = __builtin_amdgcn_exp2f(a.c2 * (2.0f * dot - nn - dnorm[u]));
+#pragma unroll
+          for (int k = 0; k < KP; ++k) part[k] = fmaf(areg[u][k], kg, part[k]);
+          if (idx >= jlo) {
+            const float g = fmaf(a.wl, dot, a.wg * kg);
+            s.gram[nmod_r * R + idx % R] = g;
+            s.gram[(idx % R) * R + nmod_r] = g;
+          }
+          const int mv = idx - evlo;
+          if (mv >= 0 && mv <= W - 2) s.evkr[nmod_w * EVS + mv] = kg;
+        }
+      }
+    } else {
+      for (int slot = tid; slot < cap && slot <= n; slot += kThreads) {
+        float* drow = a.dict + (size_t)slot * M2;
+        float* arow = a.alpha + (size_t)slot * K;
+        if (slot == sn) {
+          if (evicting) {
+            for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
+          }
+          for (int m = 0; m < M2; ++m) drow[m] = sample_comp(a.rx, M2, M, n, m);
+          for (int k = 0; k < K; ++k) arow[k] = 0.0f;
+        }
+        int back = sn - slot;
+        if (back < 0) back += cap;
+        const int idx = n - back;
+        float dot = 0.0f, dn = 0.0f;
+        for (int m = 0; m < M2; ++m) {
+          const float dv = drow[m];
+          dot = fmaf(sample_comp(a.rx, M2, M, n, m), dv, dot);
+          dn = fmaf(dv, dv, dn);
+        }
+        const float kg = __builtin_amdgcn_exp2f(a.c2 * (2.0f * dot - nn - dn));
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+          if (k < K) part[k] = fmaf(arow[k], kg, part[k]);
+        if (idx >= jlo) {
+          const float g = fmaf(a.wl, dot, a.wg * kg);
+          s.gram[nmod_r * R + idx % R] = g;
+          s.gram[(idx % R) * R + nmod_r] = g;
+        }
+        const int mv = idx - evlo;
+        if (mv >= 0 && mv <= W - 2) s.evkr[nmod_w * EVS + mv] = kg;
+      }
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const float v = wave_sum_to_last(part[k]);
+      if (lane == 63) s.part[wave * KP + k] = v;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ phase C
+    const int L = n + 1 < W ? n + 1 : W;    // |J_n|
+    const float qscale = a.mu / s.qden[L];
+    for (int t = tid; t < L * KP; t += kThreads) {
+      const int p = t / KP, k = t - p * KP;
+      const int j = n - p, jw = j % W;
+      float c = 0.0f;
+      if (k < K) {
+        float e;
+        if (p == 0) {
+          e = 0.0f;
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) e += s.part[w * KP + k];
+          const float* wr = s.wlin + k * M2P;
+          const float* rr = s.rwin + nmod_r * M2P;
+          float l0 = 0.0f, l1 = 0.0f;
+#pragma unroll
+          for (int m = 0; m < M2P; m += 2) {
+            l0 = fmaf(wr[m], rr[m], l0);
+            l1 = fmaf(wr[m + 1], rr[m + 1], l1);
+          }
+          e += l0 + l1;
+        } else {
+          e = s.e[jw * KP + k];
+          if (evicting) e -= s.aev[k] * s.evkr[jw * EVS + (n - j - 1)];
+        }
+        s.e[jw * KP + k] = e;
+        const float b = a.sym[((size_t)(j >> 1) * K + k) * 2 + (j & 1)];
+        const float x = e - b;
+        if (!isfinite(x)) flags |= 1;
+        const float kjj = fmaf(a.wl, s.nrm[jw], a.wg);
+        const float beta = kjj > 0.0f ? -soft_threshold(x, a.eps) / kjj : 0.0f;
+        c = qscale * a.omega[p] * beta;
+      }
+      s.c[jw * KP + k] = c;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ phase D
+    for (int t = tid; t < L * KP; t += kThreads) {
+      const int p = t / KP, k = t - p * KP;
+      if (k >= K) continue;
+      const int i = n - p;
+      const int ir = i % R;
+      float de = 0.0f;
+      for (int q = 0; q < L; ++q) {
+        const int j = n - q;
+        de = fmaf(s.c[(j % W) * KP + k], s.gram[(j % R) * R + ir], de);
+      }
+      s.e[(i % W) * KP + k] += de;
+    }
+    if constexpr (SLOTS > 0) {
+#pragma unroll
+      for (int u = 0; u < SLOTS; ++u) {
+        const int slot = tid + kThreads * u;
+        if (slot < cap && slot <= n) {
+          int back = sn - slot;
+          if (back < 0) back += cap;
+          const int idx = n - back;
+          if (idx >= jlo) {
+#pragma unroll
+            for (int k = 0; k < KP; ++k) areg[u][k] = fmaf(s.c[(idx % W) * KP + k], a.wg, areg[u][k]);
+          }
+        }
+      }
+    } else {
+      // The owner of a slot updates it, so that its own reads in the next
+      // phase A see the new value without a barrier.
+      for (int q = 0; q < L; ++q) {
+        const int j = n - q;
+        const int slot = j % cap;
+        if (slot % kThreads != tid) continue;
+        float* arow = a.alpha + (size_t)slot * K;
+        for (int k = 0; k < K; ++k) arow[k] = fmaf(s.c[(j % W) * KP + k], a.wg, arow[k]);
+      }
+    }
+    for (int t = tid; t < K * M2; t += kThreads) {
+      const int k = t / M2, m = t - k * M2;
+      float acc = 0.0f;
+      for (int q = 0; q < L; ++q) {
+        const int j = n - q;
+        acc = fmaf(s.c[(j % W) * KP + k], s.rwin[(j % R) * M2P + m], acc);
+      }
+      s.wlin[k * M2P + m] = fmaf(a.wl, acc, s.wlin[k * M2P + m]);
+    }
+    // Phase A of the next step touches only ring rows that no window member
+    // of this step uses (rings of W + 1), so no barrier is needed here.
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------ write back
+  if constexpr (SLOTS > 0) {
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int slot = tid + kThreads * u;
+      if (slot < cap) {
+        float* drow = a.dict + (size_t)slot * M2;
+#pragma unroll
+        for (int mm = 0; mm < M2P; ++mm)
+          if (mm < M2) drow[mm] = dreg[u][mm];
+        float* arow = a.alpha + (size_t)slot * K;
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+          if (k < K) arow[k] = areg[u][k];
+      }
+    }
+  } else {
+    // Slots never written (T < cap) are cleared so detection may sum them.
+    for (size_t i = (size_t)T * M2 + tid; i < (size_t)cap * M2; i += kThreads) a.dict[i] = 0.0f;
+  }
+  for (int t = tid; t < K * M2; t += kThreads) {
+    const int k = t / M2, m = t - k * M2;
+    a.w[t] = s.wlin[k * M2P + m];
+  }
+  if (flags) atomicOr(&block_flags, flags);
+  __syncthreads();
+  if (tid == 0) {
+    a.state[0] = T < cap ? T : cap;
+    a.state[1] = T % cap;
+    a.state[2] = T;
+    a.state[3] = block_flags;
+  }
+}
+
+template <int M2P, int KP, int SLOTS>
+hipError_t launch_one(const TrainArgs& a, hipStream_t stream) {
+  const size_t bytes = lds_floats(a.W, KP, M2P) * sizeof(float);
+  auto kern = train_kernel<M2P, KP, SLOTS>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(1), dim3(kThreads), bytes, stream, a);
+  return hipGetLastError();
+}
+
+template <int M2P, int KP>
+hipError_t pick_slots(const TrainArgs& a, hipStream_t stream) {
+  const int slots = (a.cap + kThreads - 1) / kThreads;
+  // Registers hold SLOTS * M2P dictionary floats per thread; keep that modest
+  // (larger dictionaries stay in the model buffers).
+  if constexpr (M2P <= 128)
+    if (slots <= 1) return launch_one<M2P, KP, 1>(a, stream);
+  if constexpr (2 * M2P <= 128)
+    if (slots <= 2) return launch_one<M2P, KP, 2>(a, stream);
+  if constexpr (4 * M2P <= 128)
+    if (slots <= 4) return launch_one<M2P, KP, 4>(a, stream);
+  if constexpr (8 * M2P <= 128)
+    if (slots <= 8) return launch_one<M2P, KP, 8>(a, stream);
+  return launch_one<M2P, KP, 0>(a, stream);
+}
+
+template <int M2P>
+hipError_t pick_k(const TrainArgs& a, hipStream_t stream) {
+  if (a.K <= 4) return pick_slots<M2P, 4>(a, stream);
+  if (a.K <= 8) return pick_slots<M2P, 8>(a, stream);
+  return pick_slots<M2P, 16>(a, stream);
+}
+
+}  // namespace
+
+hipError_t launch_train(const TrainArgs& a, hipStream_t stream) {
+  if (a.M2 <= 16) return pick_k<16>(a, stream);
+  if (a.M2 <= 32) return pick_k<32>(a, stream);
+  if (a.M2 <= 64) return pick_k<64>(a, stream);
+  if (a.M2 <= 128) return pick_k<128>(a, stream);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace apsm

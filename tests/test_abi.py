@@ -1,0 +1,115 @@
+"""The C ABI on the host: the library loads, exports every function that
+include/apsm.h declares, and rejects invalid arguments before touching the
+device (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2201_05024_amd as A
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "apsm.h")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(A.LIB_PATH),
+                               reason="libapsm.so not built (run python -m paper_2201_05024_amd.build)")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(apsm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("apsm_train", "apsm_detect", "apsm_get_status", "apsm_strerror",
+                     "apsm_last_hip_error", "apsm_version"):
+        assert required in names
+
+
+@needs_lib
+def test_every_declared_symbol_is_exported():
+    L = A.library()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+@needs_lib
+def test_strerror_and_version():
+    L = A.library()
+    assert L.apsm_version().decode().count(".") == 2
+    for code in range(0, 6):
+        assert isinstance(L.apsm_strerror(code), bytes) and L.apsm_strerror(code)
+
+
+def _model(M2=32, K=6, cap=256, ptr=1):
+    return A._CModel(M2, K, cap, 0, ptr, ptr, ptr, ptr)
+
+
+def _params(**kw):
+    base = dict(sigma2=0.5, eps=0.05, mu=1.0, w_lin=0.5, w_gauss=0.5, window=16, dict_cap=256,
+                reserved=0, pos_weights=None)
+    base.update(kw)
+    return A._CParams(**base)
+
+
+BAD_TRAIN = [
+    (dict(sigma2=0.0), 1), (dict(sigma2=float("nan")), 1), (dict(eps=-0.1), 1),
+    (dict(mu=0.0), 1), (dict(mu=2.0), 1), (dict(w_lin=0.0, w_gauss=0.0), 1),
+    (dict(w_lin=-1.0), 1), (dict(window=0), 1), (dict(window=65, dict_cap=256), 3),
+    (dict(dict_cap=8, window=16), 1), (dict(reserved=1), 1),
+]
+
+
+@needs_lib
+@pytest.mark.parametrize("kw,code", BAD_TRAIN)
+def test_train_rejects_bad_params(kw, code):
+    L = A.library()
+    p = _params(**kw)
+    cap = kw.get("dict_cap", 256)
+    m = _model(cap=cap)
+    assert L.apsm_train(ctypes.byref(p), 32, 6, 64, 1, 1, ctypes.byref(m), None) == code
+
+
+@needs_lib
+def test_train_rejects_bad_shapes_and_pointers():
+    L = A.library()
+    p = _params()
+    m = _model()
+    assert L.apsm_train(ctypes.byref(p), 32, 6, 64, None, 1, ctypes.byref(m), None) == 1
+    assert L.apsm_train(None, 32, 6, 64, 1, 1, ctypes.byref(m), None) == 1
+    assert L.apsm_train(ctypes.byref(p), 32, 6, 0, 1, 1, ctypes.byref(m), None) == 2
+    assert L.apsm_train(ctypes.byref(p), 31, 6, 64, 1, 1, ctypes.byref(_model(M2=31)), None) == 2
+    assert L.apsm_train(ctypes.byref(p), 32, 5, 64, 1, 1, ctypes.byref(m), None) == 2   # K mismatch
+    assert L.apsm_train(ctypes.byref(p), 256, 6, 64, 1, 1, ctypes.byref(_model(M2=256)), None) == 3
+    assert L.apsm_train(ctypes.byref(p), 32, 17, 64, 1, 1, ctypes.byref(_model(K=17)), None) == 3
+    assert L.apsm_train(ctypes.byref(p), 32, 6, 64, 1, 1, ctypes.byref(_model(ptr=None)), None) == 1
+    bad_w = (ctypes.c_float * 16)(*([1.0] * 15 + [0.0]))
+    pw = _params(pos_weights=ctypes.cast(bad_w, ctypes.POINTER(ctypes.c_float)))
+    assert L.apsm_train(ctypes.byref(pw), 32, 6, 64, 1, 1, ctypes.byref(m), None) == 1
+
+
+@needs_lib
+def test_detect_rejects_bad_args():
+    L = A.library()
+    m = _model()
+    ok = dict(sigma2=0.5, S=10, rx=1, soft=1, hard=None, mod=0, truth=None, err=None)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return L.apsm_detect(ctypes.byref(a.pop("model", m)), a["sigma2"], a["S"], a["rx"],
+                             a["soft"], a["hard"], a["mod"], a["truth"], a["err"], None)
+
+    assert call(sigma2=0.0) == 1
+    assert call(S=-1) == 2
+    assert call(mod=3) == 1
+    assert call(hard=1, mod=0) == 1                     # decisions need a modulation
+    assert call(truth=1, mod=2) == 1                    # truth without a counter
+    assert call(soft=None) == 1                         # nothing to produce
+    assert call(rx=None) == 1
+    assert call(model=_model(M2=7)) == 2
+    assert call(model=_model(K=0)) == 2
+    assert call(S=0) == 0                               # empty input: nothing launched
+    assert call(S=0, rx=None, soft=None) == 0           # ... and no buffers needed

@@ -1,0 +1,243 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded float32 inputs.  Rules and tolerances: tests/parity_util.py."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+import paper_2201_05024_amd as A
+from parity_util import (REL_TOL, compare_hard, compare_soft, oracle_model_to_ring,
+                         oracle_params, ring_to_oracle_model, rounded)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def announce(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+# ------------------------------------------------------------ detection only
+
+def test_detect_golden_two_entries():
+    fx = json.load(open(os.path.join(GOLDEN, "detect_two_entries.json")))
+    m = A.Model(2, 1, 2, DEV, fx["sigma2"])
+    m.dict.copy_(cuda(np.array(fx["dict"], dtype=np.float32)))
+    m.alpha.copy_(cuda(np.array(fx["alpha"], dtype=np.float32)))
+    m.w.copy_(cuda(np.array(fx["w"], dtype=np.float32)))
+    m.state.copy_(cuda(np.array([2, 0, 2, 0], dtype=np.int32)))
+    out = A.detect(m, cuda(np.array(fx["rx"], dtype=np.float32)), modulation=None)
+    np.testing.assert_allclose(out["soft"].cpu().numpy(), fx["expected_soft"], atol=2e-6)
+
+
+DETECT_CASES = [
+    # K, M, P, S, cap, W, modulation
+    (4, 8, 256, 2048, 256, 16, "qpsk"),
+    (3, 3, 60, 1001, 70, 8, "qpsk"),        # M2 = 6 padded to 16; ragged D and S
+    (1, 1, 20, 65, 33, 4, "qpsk"),
+    (5, 12, 80, 333, 150, 10, "qam16"),     # M2 = 24 padded to 32
+    (9, 16, 100, 77, 200, 16, "qpsk"),      # K > 8: one column tile per wave
+    (16, 64, 64, 300, 100, 8, "qam16"),     # M2 = 128
+    (6, 32, 40, 129, 80, 32, "qpsk"),       # M2 = 64
+]
+
+
+@pytest.mark.parametrize("K,M,P,S,cap,W,mod", DETECT_CASES)
+def test_detect_only_parity(K, M, P, S, cap, W, mod):
+    """Oracle-trained model rounded to float32 -> GPU detect vs oracle detect."""
+    announce(f"detect-only K={K} M={M} P={P} S={S} cap={cap} W={W} {mod}")
+    inst = synth.make_instance(synth.InstanceSpec(K=K, M=M, P=P, S=S, snr_db=12, modulation=mod,
+                                                  seed=1000 + K * 7 + M))
+    p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=W, dict_cap=cap)
+    f = rounded(O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, oracle_params(p)))
+    d, al = oracle_model_to_ring(f, cap)
+    m = A.Model(2 * M, K, cap, DEV, p.sigma2)
+    m.dict.copy_(cuda(d.astype(np.float32)))
+    m.alpha.copy_(cuda(al.astype(np.float32)))
+    m.w.copy_(cuda(f.w.astype(np.float32)))
+    m.state.copy_(cuda(np.array([len(f.dict_vec), 0, 2 * P, 0], dtype=np.int32)))
+    out = A.detect(m, cuda(inst.rx_data), modulation=mod, truth=cuda(inst.truth))
+    torch.cuda.synchronize()
+    soft_ref = O.detect_planar(f, inst.rx_data)
+    worst, _ = compare_soft(out["soft"].cpu().numpy(), soft_ref, mod)
+    assert worst <= REL_TOL, worst
+    hard = out["hard"].cpu().numpy()
+    outside, inside = compare_hard(hard, soft_ref, mod)
+    assert outside == 0, (outside, inside)
+    np.testing.assert_array_equal(out["errors"].cpu().numpy(), O.symbol_errors(hard, inst.truth))
+
+
+# ------------------------------------------------------------------ end to end
+
+E2E_CASES = {
+    # name: (spec kwargs, Params kwargs)
+    "plain_small": (dict(K=4, M=8, P=256, S=2048, snr_db=10.0), dict(window=16, dict_cap=256)),
+    "uncapped": (dict(K=4, M=8, P=128, S=500, snr_db=10.0), dict(window=16, dict_cap=256)),
+    "window1": (dict(K=3, M=4, P=100, S=300, snr_db=15.0), dict(window=1, dict_cap=64)),
+    "window64": (dict(K=4, M=8, P=150, S=300, snr_db=10.0), dict(window=64, dict_cap=64)),
+    "mu_half": (dict(K=4, M=8, P=128, S=300, snr_db=10.0), dict(window=8, dict_cap=100, mu=0.5)),
+    "mu_1p5": (dict(K=4, M=8, P=128, S=300, snr_db=10.0), dict(window=8, dict_cap=100, mu=1.5)),
+    "linear_only": (dict(K=4, M=8, P=128, S=300, snr_db=10.0), dict(window=8, dict_cap=64, w_gauss=0.0, w_lin=1.0)),
+    "gauss_only": (dict(K=4, M=8, P=128, S=300, snr_db=10.0), dict(window=8, dict_cap=64, w_lin=0.0, w_gauss=1.0)),
+    "eps0": (dict(K=2, M=4, P=100, S=300, snr_db=10.0), dict(window=8, dict_cap=64, eps=0.0)),
+    "pos_weights": (dict(K=4, M=8, P=128, S=300, snr_db=10.0),
+                    dict(window=6, dict_cap=60, pos_weights=[3.0, 2.0, 1.0, 0.5, 0.25, 0.125])),
+    "qam16": (dict(K=3, M=8, P=200, S=400, snr_db=25.0, modulation="qam16"), dict(window=16, dict_cap=256)),
+    "k1_m1": (dict(K=1, M=1, P=64, S=100, snr_db=20.0), dict(window=4, dict_cap=32)),
+    "odd_m": (dict(K=2, M=3, P=90, S=211, snr_db=12.0), dict(window=5, dict_cap=77)),
+    "k16_m64": (dict(K=16, M=64, P=96, S=130, snr_db=20.0, modulation="qam16"), dict(window=16, dict_cap=128)),
+    "model_buffer_path": (dict(K=6, M=32, P=300, S=200, snr_db=10.0), dict(window=32, dict_cap=520)),
+    "sigma_paper": (dict(K=6, M=16, P=160, S=300, snr_db=20.0), dict(window=20, dict_cap=320, sigma2=0.05)),
+    "near_far_rapp": (dict(K=6, M=16, P=256, S=512, snr_db=10.0, near_far_db=(-6.0, 0.0), rapp=(2.0, 1.0)),
+                      dict(window=32, dict_cap=256)),
+}
+
+
+def run_e2e(spec_kw, par_kw, seed):
+    spec = synth.InstanceSpec(seed=seed, **spec_kw)
+    inst = synth.make_instance(spec)
+    p = A.Params(**{"sigma2": 0.5, "eps": 0.05, "mu": 1.0, **par_kw})
+    m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
+    out = A.detect(m, cuda(inst.rx_data), modulation=spec.modulation, truth=cuda(inst.truth))
+    torch.cuda.synchronize()
+    return inst, p, m, out
+
+
+@pytest.mark.parametrize("name", list(E2E_CASES))
+def test_end_to_end_parity(name):
+    spec_kw, par_kw = E2E_CASES[name]
+    announce(f"end-to-end {name} {spec_kw} {par_kw}")
+    inst, p, m, out = run_e2e(spec_kw, par_kw, seed=2000 + len(name))
+    mod = inst.spec.modulation
+    f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, oracle_params(p))
+    st = m.status()
+    T = 2 * inst.spec.P
+    assert st == {"size": min(T, p.dict_cap), "head": T % p.dict_cap, "steps": T, "flags": 0}
+    # the trained model itself
+    w_gpu = m.w.cpu().numpy().astype(np.float64)
+    scale_w = max(np.abs(f.w).max(), 1e-3)
+    assert np.abs(w_gpu - f.w).max() <= REL_TOL * scale_w
+    d_ref, a_ref = oracle_model_to_ring(f, p.dict_cap)
+    np.testing.assert_array_equal(m.dict.cpu().numpy(), d_ref.astype(np.float32))
+    if p.w_gauss > 0:
+        scale_a = max(np.abs(a_ref).max(), 1e-3)
+        assert np.abs(m.alpha.cpu().numpy() - a_ref).max() <= REL_TOL * scale_a
+    # detection
+    soft_ref = O.detect_planar(f, inst.rx_data)
+    worst, _ = compare_soft(out["soft"].cpu().numpy(), soft_ref, mod)
+    assert worst <= REL_TOL, worst
+    hard = out["hard"].cpu().numpy()
+    outside, inside = compare_hard(hard, soft_ref, mod)
+    assert outside == 0, (outside, inside)
+    errs = out["errors"].cpu().numpy()
+    np.testing.assert_array_equal(errs, O.symbol_errors(hard, inst.truth))
+    print(f"[result] {name}: worst scaled err {worst:.2e}, band mismatches {inside}, "
+          f"SER gpu {errs.sum() / hard.size:.4g}", flush=True)
+
+
+# --------------------------------------------------- full-size slot, sampled
+
+def test_full_slot_sampled_parity():
+    """Realistic slot (K=6, 16 antennas, near-far, Rapp PA, 1024 pilots,
+    1,048,576 data symbols, W=32, cap 1024) at 5 dB, in the launch
+    configuration the benchmark times; the oracle evaluates a sample of the
+    outputs one by one."""
+    announce("full slot 5 dB, S=1048576")
+    spec = synth.spec_slot(5.0)
+    inst = synth.make_instance(spec)
+    p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, dict_cap=1024)
+    m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
+    out = A.detect(m, cuda(inst.rx_data), modulation="qpsk", truth=cuda(inst.truth))
+    torch.cuda.synchronize()
+    f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, oracle_params(p))
+    assert np.abs(m.w.cpu().numpy() - f.w).max() <= REL_TOL * np.abs(f.w).max()
+    rng = np.random.default_rng(7)
+    S = spec.S
+    idx = np.unique(np.concatenate([np.arange(256), np.arange(S - 256, S),
+                                    rng.integers(0, S, 1536)]))
+    soft_ref = O.detect_planar(f, inst.rx_data[idx])
+    soft = out["soft"].cpu().numpy()[idx]
+    worst, _ = compare_soft(soft, soft_ref, "qpsk")
+    assert worst <= REL_TOL, worst
+    hard = out["hard"].cpu().numpy()
+    outside, inside = compare_hard(hard[idx], soft_ref, "qpsk")
+    assert outside == 0, (outside, inside)
+    errs = out["errors"].cpu().numpy()
+    np.testing.assert_array_equal(errs, O.symbol_errors(hard, inst.truth))
+    # SER on the sampled symbols is identical when no decision fell in the band
+    if inside == 0:
+        ref_lab = O.decide(soft_ref, "qpsk")
+        np.testing.assert_array_equal(O.symbol_errors(ref_lab, inst.truth[idx]),
+                                      O.symbol_errors(hard[idx], inst.truth[idx]))
+    print(f"[result] full slot: worst {worst:.2e}, SER {errs.sum() / hard.size:.4g}", flush=True)
+
+
+# ----------------------------------------------------------------- behaviour
+
+def test_errors_accumulate_and_outputs_optional():
+    inst = synth.make_instance(synth.InstanceSpec(K=3, M=4, P=64, S=500, snr_db=0.0, seed=5))
+    p = A.Params(window=8, dict_cap=64)
+    m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
+    rx, truth = cuda(inst.rx_data), cuda(inst.truth)
+    full = A.detect(m, rx, truth=truth)
+    e1 = full["errors"].clone()
+    assert int(e1.sum()) > 0                          # 0 dB: some errors to count
+    A.detect(m, rx, truth=truth, errors=full["errors"], want_soft=False, want_hard=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(full["errors"].cpu().numpy(), 2 * e1.cpu().numpy())
+    only_hard = A.detect(m, rx, want_soft=False)
+    assert only_hard["soft"] is None
+    assert torch.equal(only_hard["hard"], full["hard"])
+    soft_only = A.detect(m, rx, modulation=None)
+    assert soft_only["hard"] is None and torch.equal(soft_only["soft"], full["soft"])
+
+
+@pytest.mark.parametrize("S", [0, 1, 15, 16, 17, 127, 128, 129])
+def test_ragged_and_empty_inputs(S):
+    inst = synth.make_instance(synth.InstanceSpec(K=2, M=4, P=40, S=max(S, 1), snr_db=10.0, seed=9))
+    p = A.Params(window=4, dict_cap=40)
+    m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
+    rx = cuda(inst.rx_data[:S])
+    soft = torch.full((S, 2, 2), 123.0, device=DEV)
+    hard = torch.full((S, 2), 255, dtype=torch.uint8, device=DEV)
+    A.detect(m, rx, soft=soft, hard=hard)
+    torch.cuda.synchronize()
+    if S == 0:
+        return
+    f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, oracle_params(p))
+    ref = O.detect_planar(f, inst.rx_data[:S])
+    worst, _ = compare_soft(soft.cpu().numpy(), ref, "qpsk")
+    assert worst <= REL_TOL
+
+
+def test_deterministic():
+    inst = synth.make_instance(synth.InstanceSpec(K=6, M=16, P=300, S=5000, snr_db=8.0, seed=11))
+    p = A.Params(window=32, dict_cap=256)
+    outs = []
+    for _ in range(2):
+        m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
+        o = A.detect(m, cuda(inst.rx_data), truth=cuda(inst.truth))
+        torch.cuda.synchronize()
+        outs.append((m.dict.clone(), m.alpha.clone(), m.w.clone(), o["soft"], o["hard"], o["errors"]))
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)
+
+
+def test_nonfinite_training_input_flagged():
+    inst = synth.make_instance(synth.InstanceSpec(K=2, M=4, P=40, S=10, snr_db=10.0, seed=12))
+    rx = inst.rx_pilot.copy()
+    rx[7, 3] = np.nan
+    m = A.train(cuda(rx), cuda(inst.sym_pilot), A.Params(window=4, dict_cap=40))
+    assert m.status()["flags"] & 1
+    m2 = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), A.Params(window=4, dict_cap=40), model=m)
+    assert m2.status()["flags"] == 0
