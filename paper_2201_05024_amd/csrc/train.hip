@@ -53,44 +53,52 @@ __device__ __forceinline__ float soft_threshold(float x, float eps) {
   return m > 0.0f ? copysignf(m, x) : 0.0f;
 }
 
-// Shared-memory layout, sized at launch from W, K and M2P.
+// Shared-memory layout, sized at launch from W, K and M2P.  Rings indexed by
+// the training index modulo W (or R = W + 1) hold the window members.  The
+// rings that phase D sweeps are stored twice (rows r and r + size), so that
+// the L newest members are the contiguous rows base - L + 1 .. base with
+// base = (n mod size) + size: the sweeps run with constant strides and no
+// wrap-around arithmetic.
 struct Lds {
-  float* gram;   // [R][R], R = W + 1 (ring over window members)
+  float* gram;   // [2R][R]  K(r_j, r_i) of window members (rows doubled)
   float* evkr;   // [W][W-1] kappa_G(r_j, d_v) for the entries v evicted while j is in the window
-  float* e;      // [W][KP] running predictions f(r_j)
-  float* c;      // [W][KP] mu q_j beta_jk of the current step
-  float* nrm;    // [W] ||r_j||^2
-  float* rwin;   // [R][M2P] window members' vectors
-  float* wlin;   // [KP][M2P] linear coefficients
-  float* part;   // [kWaves][KP] per-wave partial sums of the Gaussian part of f_n(r_n)
-  float* aev;    // [KP] coefficients of the evicted entry
-  float* qden;   // [W+1] prefix sums of omega
+  float* e;      // [W][KP]  running predictions f(r_j)
+  float* c;      // [2W][KP] mu q_j beta_jk of the current step (rows doubled)
+  float* bwin;   // [W][KP]  training symbols b_j of the window members
+  float* nrm;    // [W]      ||r_j||^2
+  float* rwin;   // [2R][M2P] window members' vectors and r_{n+1} (rows doubled)
+  float* part;   // [kWaves][KP] per-wave partial sums of f_n(r_n)
+  float* aev;    // [KP]     coefficients of the evicted entry
+  float* omega;  // [W]      position weights
+  float* qden;   // [W+1]    prefix sums of omega
 };
 
 __host__ __device__ inline size_t lds_floats(int W, int KP, int M2P) {
-  int R = W + 1;
-  return (size_t)R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 2 * (size_t)W * KP + W +
-         (size_t)R * M2P + (size_t)KP * M2P + kWaves * KP + KP + (W + 1);
+  const size_t R = W + 1;
+  return 2 * R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 4 * (size_t)W * KP + W +
+         2 * R * M2P + kWaves * KP + KP + W + (W + 1);
 }
 
 __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
   Lds s;
-  int R = W + 1;
+  const int R = W + 1;
   float* p = base;
-  s.gram = p; p += R * R;
+  s.gram = p; p += 2 * R * R;
   s.evkr = p; p += W * (W > 1 ? W - 1 : 1);
   s.e = p; p += W * KP;
-  s.c = p; p += W * KP;
+  s.c = p; p += 2 * W * KP;
+  s.bwin = p; p += W * KP;
   s.nrm = p; p += W;
-  s.rwin = p; p += R * M2P;
-  s.wlin = p; p += KP * M2P;
+  s.rwin = p; p += 2 * R * M2P;
   s.part = p; p += kWaves * KP;
   s.aev = p; p += KP;
+  s.omega = p; p += W;
   s.qden = p;
   return s;
 }
 
-// Component m of r_n (zero in the padding m >= M2).
+// Component m of r_n (zero in the padding m >= M2):
+// r_{2t} = r1(t) = x_t, r_{2t+1} = r2(t) = [x_{t,M..2M-1}; -x_{t,0..M-1}].
 __device__ __forceinline__ float sample_comp(const float* rx, int M2, int M, int n, int m) {
   if (m >= M2) return 0.0f;
   const float* src = rx + (size_t)(n >> 1) * M2;
@@ -98,21 +106,61 @@ __device__ __forceinline__ float sample_comp(const float* rx, int M2, int M, int
   return m < M ? src[m + M] : -src[m - M];
 }
 
+// a - b mod `mod` for 0 <= a < mod, 0 <= b < mod (ring index without division)
+__device__ __forceinline__ int ring_sub(int a, int b, int mod) {
+  const int r = a - b;
+  return r < 0 ? r + mod : r;
+}
+
+// sum_{q < L} x[-q * xs] * y[-q * ys], eight loads in flight per round.
+__device__ __forceinline__ float sweep(const float* x, int xs, const float* y, int ys, int L) {
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  int q = 0;
+  for (; q + 4 <= L; q += 4) {
+    a0 = fmaf(x[-q * xs], y[-q * ys], a0);
+    a1 = fmaf(x[-(q + 1) * xs], y[-(q + 1) * ys], a1);
+    a2 = fmaf(x[-(q + 2) * xs], y[-(q + 2) * ys], a2);
+    a3 = fmaf(x[-(q + 3) * xs], y[-(q + 3) * ys], a3);
+  }
+  for (; q < L; ++q) a0 = fmaf(x[-q * xs], y[-q * ys], a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
 template <int M2P, int KP, int SLOTS>
 __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   extern __shared__ float lds_raw[];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int W = a.W, R = W + 1, cap = a.cap, K = a.K, M2 = a.M2, M = a.M;
   const int T = 2 * a.P;
   const int EVS = W > 1 ? W - 1 : 1;
+  const int KM = K * M2;
   Lds s = carve(lds_raw, W, KP, M2P);
 
-  for (int i = tid; i < KP * M2P; i += kThreads) s.wlin[i] = 0.0f;
-  for (int i = tid; i < W * KP; i += kThreads) { s.e[i] = 0.0f; s.c[i] = 0.0f; }
+  for (int i = tid; i < W * KP; i += kThreads) {
+    s.e[i] = 0.0f;
+    s.c[i] = 0.0f;
+    s.c[i + W * KP] = 0.0f;
+    s.bwin[i] = 0.0f;
+  }
+  if (tid < W) s.omega[tid] = a.omega[tid];
   if (tid == 0) {
     float acc = 0.0f;
     s.qden[0] = 0.0f;
     for (int p = 0; p < W; ++p) { acc += a.omega[p]; s.qden[p + 1] = acc; }
+  }
+
+  // Linear coefficients: entry e = k * M2 + m lives in a register of thread
+  // e % kThreads, which both updates it and uses it for f_n(r_n).
+  constexpr int WPT = (KP * M2P + kThreads - 1) / kThreads;
+  float wreg[WPT];
+  int wk[WPT], wm[WPT];
+#pragma unroll
+  for (int u = 0; u < WPT; ++u) {
+    const int e = tid + kThreads * u;
+    wreg[u] = 0.0f;
+    wk[u] = e < KM ? e / M2 : KP;           // KP marks "no entry"
+    wm[u] = e < KM ? e - (e / M2) * M2 : 0;
   }
 
   // Register-resident slots (SLOTS > 0): slot tid + kThreads * u.
@@ -135,37 +183,54 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   __shared__ int block_flags;
   if (tid == 0) block_flags = 0;
   int flags = 0;
+
+  // Global inputs are read one step ahead, so their latency overlaps the
+  // previous step: component tid of r_{n+1} (stored into the vector ring in
+  // phase C) and b_{k,n+1} for thread k.
+  float comp_nx = 0.0f, bv = 0.0f, bv_nx = 0.0f;
+  if (tid < M2P) {
+    const float c0 = sample_comp(a.rx, M2, M, 0, tid);
+    s.rwin[tid] = c0;
+    s.rwin[R * M2P + tid] = c0;
+  }
+  bv = tid < K ? a.sym[tid * 2] : 0.0f;
   __syncthreads();
 
+  int sn = 0, nw = 0, nr = 0;               // n % cap, n % W, n % R
   for (int n = 0; n < T; ++n) {
+    if (n + 1 < T) {
+      comp_nx = tid < M2P ? sample_comp(a.rx, M2, M, n + 1, tid) : 0.0f;
+      bv_nx = tid < K ? a.sym[((size_t)((n + 1) >> 1) * K + tid) * 2 + ((n + 1) & 1)] : 0.0f;
+    }
+
     // ------------------------------------------------------------ phase A
-    // r_n is kept in registers by the register path; the model-buffer path
-    // re-reads its components (L1 hits) to stay clear of large arrays.
+    const float* rrow = s.rwin + nr * M2P;  // r_n
     float rn[SLOTS > 0 ? M2P : 1];
     float nn = 0.0f;
     if constexpr (SLOTS > 0) {
 #pragma unroll
       for (int m = 0; m < M2P; ++m) {
-        rn[m] = sample_comp(a.rx, M2, M, n, m);
+        rn[m] = rrow[m];
         nn = fmaf(rn[m], rn[m], nn);
       }
     } else {
-      for (int m = 0; m < M2; ++m) {
-        const float v = sample_comp(a.rx, M2, M, n, m);
-        nn = fmaf(v, v, nn);
-      }
+      for (int m = 0; m < M2; ++m) nn = fmaf(rrow[m], rrow[m], nn);
     }
-    const int sn = n % cap;                 // slot of r_n
     const bool evicting = n >= cap;
-    const int nmod_r = n % R, nmod_w = n % W;
-    const int jlo = n - W + 1;              // window members have index >= jlo
+    const int L = n + 1 < W ? n + 1 : W;    // |J_n|
     const int evlo = n - cap + 1;           // oldest entry in the dictionary after the append
-    if (tid < M2P) s.rwin[nmod_r * M2P + tid] = sample_comp(a.rx, M2, M, n, tid);
-    if (tid == 0) s.nrm[nmod_w] = nn;
+    if (tid < KP) s.bwin[nw * KP + tid] = bv;
+    if (tid == 0) s.nrm[nw] = nn;
 
     float part[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) part[k] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const float prod = wreg[u] * rrow[wm[u]];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) part[k] += (wk[u] == k) ? prod : 0.0f;
+    }
 
     if constexpr (SLOTS > 0) {
 #pragma unroll
@@ -183,22 +248,23 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
           for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
         }
         if (slot < cap && slot <= n) {
-          int back = sn - slot;
-          if (back < 0) back += cap;
-          const int idx = n - back;         // training index held by this slot
+          const int back = ring_sub(sn, slot, cap);   // this slot holds sample n - back
           float dot = 0.0f;
 #pragma unroll
           for (int m = 0; m < M2P; ++m) dot = fmaf(rn[m], dreg[u][m], dot);
           const float kg = __builtin_amdgcn_exp2f(a.c2 * (2.0f * dot - nn - dnorm[u]));
 #pragma unroll
           for (int k = 0; k < KP; ++k) part[k] = fmaf(areg[u][k], kg, part[k]);
-          if (idx >= jlo) {
+          if (back < L) {
+            const int ir = ring_sub(nr, back, R);
             const float g = fmaf(a.wl, dot, a.wg * kg);
-            s.gram[nmod_r * R + idx % R] = g;
-            s.gram[(idx % R) * R + nmod_r] = g;
+            s.gram[nr * R + ir] = g;
+            s.gram[(nr + R) * R + ir] = g;
+            s.gram[ir * R + nr] = g;
+            s.gram[(ir + R) * R + nr] = g;
           }
-          const int mv = idx - evlo;
-          if (mv >= 0 && mv <= W - 2) s.evkr[nmod_w * EVS + mv] = kg;
+          const int mv = n - back - evlo;
+          if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
         }
       }
     } else {
@@ -209,32 +275,32 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
           if (evicting) {
             for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
           }
-          for (int m = 0; m < M2; ++m) drow[m] = sample_comp(a.rx, M2, M, n, m);
+          for (int m = 0; m < M2; ++m) drow[m] = rrow[m];
           for (int k = 0; k < K; ++k) arow[k] = 0.0f;
         }
-        int back = sn - slot;
-        if (back < 0) back += cap;
-        const int idx = n - back;
+        const int back = ring_sub(sn, slot, cap);
         float dot = 0.0f, dn = 0.0f;
         for (int m = 0; m < M2; ++m) {
           const float dv = drow[m];
-          dot = fmaf(sample_comp(a.rx, M2, M, n, m), dv, dot);
+          dot = fmaf(rrow[m], dv, dot);
           dn = fmaf(dv, dv, dn);
         }
         const float kg = __builtin_amdgcn_exp2f(a.c2 * (2.0f * dot - nn - dn));
 #pragma unroll
         for (int k = 0; k < KP; ++k)
           if (k < K) part[k] = fmaf(arow[k], kg, part[k]);
-        if (idx >= jlo) {
+        if (back < L) {
+          const int ir = ring_sub(nr, back, R);
           const float g = fmaf(a.wl, dot, a.wg * kg);
-          s.gram[nmod_r * R + idx % R] = g;
-          s.gram[(idx % R) * R + nmod_r] = g;
+          s.gram[nr * R + ir] = g;
+          s.gram[(nr + R) * R + ir] = g;
+          s.gram[ir * R + nr] = g;
+          s.gram[(ir + R) * R + nr] = g;
         }
-        const int mv = idx - evlo;
-        if (mv >= 0 && mv <= W - 2) s.evkr[nmod_w * EVS + mv] = kg;
+        const int mv = n - back - evlo;
+        if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
       }
     }
-    const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const float v = wave_sum_to_last(part[k]);
@@ -243,11 +309,10 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     __syncthreads();
 
     // ------------------------------------------------------------ phase C
-    const int L = n + 1 < W ? n + 1 : W;    // |J_n|
     const float qscale = a.mu / s.qden[L];
     for (int t = tid; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
-      const int j = n - p, jw = j % W;
+      const int jw = ring_sub(nw, p, W);
       float c = 0.0f;
       if (k < K) {
         float e;
@@ -255,55 +320,46 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
           e = 0.0f;
 #pragma unroll
           for (int w = 0; w < kWaves; ++w) e += s.part[w * KP + k];
-          const float* wr = s.wlin + k * M2P;
-          const float* rr = s.rwin + nmod_r * M2P;
-          float l0 = 0.0f, l1 = 0.0f;
-#pragma unroll
-          for (int m = 0; m < M2P; m += 2) {
-            l0 = fmaf(wr[m], rr[m], l0);
-            l1 = fmaf(wr[m + 1], rr[m + 1], l1);
-          }
-          e += l0 + l1;
         } else {
           e = s.e[jw * KP + k];
-          if (evicting) e -= s.aev[k] * s.evkr[jw * EVS + (n - j - 1)];
+          if (evicting) e -= s.aev[k] * s.evkr[jw * EVS + (p - 1)];
         }
         s.e[jw * KP + k] = e;
-        const float b = a.sym[((size_t)(j >> 1) * K + k) * 2 + (j & 1)];
-        const float x = e - b;
+        const float x = e - s.bwin[jw * KP + k];
         if (!isfinite(x)) flags |= 1;
         const float kjj = fmaf(a.wl, s.nrm[jw], a.wg);
         const float beta = kjj > 0.0f ? -soft_threshold(x, a.eps) / kjj : 0.0f;
-        c = qscale * a.omega[p] * beta;
+        c = qscale * s.omega[p] * beta;
       }
       s.c[jw * KP + k] = c;
+      s.c[(jw + W) * KP + k] = c;
+    }
+    if (tid < M2P && n + 1 < T) {           // r_{n+1} into its ring row (no member of J_n)
+      const int nr1 = nr + 1 == R ? 0 : nr + 1;
+      s.rwin[nr1 * M2P + tid] = comp_nx;
+      s.rwin[(nr1 + R) * M2P + tid] = comp_nx;
     }
     __syncthreads();
 
     // ------------------------------------------------------------ phase D
+    const float* cbase = s.c + (nw + W) * KP;       // member n - q at cbase - q * KP
     for (int t = tid; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
       if (k >= K) continue;
-      const int i = n - p;
-      const int ir = i % R;
-      float de = 0.0f;
-      for (int q = 0; q < L; ++q) {
-        const int j = n - q;
-        de = fmaf(s.c[(j % W) * KP + k], s.gram[(j % R) * R + ir], de);
-      }
-      s.e[(i % W) * KP + k] += de;
+      const int ir = ring_sub(nr, p, R);
+      const float de = sweep(cbase + k, KP, s.gram + (nr + R) * R + ir, R, L);
+      s.e[ring_sub(nw, p, W) * KP + k] += de;
     }
     if constexpr (SLOTS > 0) {
 #pragma unroll
       for (int u = 0; u < SLOTS; ++u) {
         const int slot = tid + kThreads * u;
         if (slot < cap && slot <= n) {
-          int back = sn - slot;
-          if (back < 0) back += cap;
-          const int idx = n - back;
-          if (idx >= jlo) {
+          const int back = ring_sub(sn, slot, cap);
+          if (back < L) {
+            const float* cj = cbase - back * KP;
 #pragma unroll
-            for (int k = 0; k < KP; ++k) areg[u][k] = fmaf(s.c[(idx % W) * KP + k], a.wg, areg[u][k]);
+            for (int k = 0; k < KP; ++k) areg[u][k] = fmaf(cj[k], a.wg, areg[u][k]);
           }
         }
       }
@@ -311,24 +367,27 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
       // The owner of a slot updates it, so that its own reads in the next
       // phase A see the new value without a barrier.
       for (int q = 0; q < L; ++q) {
-        const int j = n - q;
-        const int slot = j % cap;
-        if (slot % kThreads != tid) continue;
+        const int slot = ring_sub(sn, q, cap);
+        if ((slot & (kThreads - 1)) != tid) continue;
+        const float* cj = cbase - q * KP;
         float* arow = a.alpha + (size_t)slot * K;
-        for (int k = 0; k < K; ++k) arow[k] = fmaf(s.c[(j % W) * KP + k], a.wg, arow[k]);
+        for (int k = 0; k < K; ++k) arow[k] = fmaf(cj[k], a.wg, arow[k]);
       }
     }
-    for (int t = tid; t < K * M2; t += kThreads) {
-      const int k = t / M2, m = t - k * M2;
-      float acc = 0.0f;
-      for (int q = 0; q < L; ++q) {
-        const int j = n - q;
-        acc = fmaf(s.c[(j % W) * KP + k], s.rwin[(j % R) * M2P + m], acc);
-      }
-      s.wlin[k * M2P + m] = fmaf(a.wl, acc, s.wlin[k * M2P + m]);
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      if (wk[u] >= KP) continue;
+      const float acc = sweep(cbase + wk[u], KP, s.rwin + (nr + R) * M2P + wm[u], M2P, L);
+      wreg[u] = fmaf(a.wl, acc, wreg[u]);
     }
     // Phase A of the next step touches only ring rows that no window member
-    // of this step uses (rings of W + 1), so no barrier is needed here.
+    // of this step uses (the Gram and vector rings have W + 1 rows; the
+    // W-rows rings are read only in phase C), so no barrier is needed here.
+
+    bv = bv_nx;
+    sn = sn + 1 == cap ? 0 : sn + 1;
+    nw = nw + 1 == W ? 0 : nw + 1;
+    nr = nr + 1 == R ? 0 : nr + 1;
   }
   __syncthreads();
 
@@ -352,10 +411,9 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     // Slots never written (T < cap) are cleared so detection may sum them.
     for (size_t i = (size_t)T * M2 + tid; i < (size_t)cap * M2; i += kThreads) a.dict[i] = 0.0f;
   }
-  for (int t = tid; t < K * M2; t += kThreads) {
-    const int k = t / M2, m = t - k * M2;
-    a.w[t] = s.wlin[k * M2P + m];
-  }
+#pragma unroll
+  for (int u = 0; u < WPT; ++u)
+    if (wk[u] < KP) a.w[tid + kThreads * u] = wreg[u];
   if (flags) atomicOr(&block_flags, flags);
   __syncthreads();
   if (tid == 0) {
