@@ -100,6 +100,11 @@ typedef struct apsm_params {
  *  state  int32[4]        written by training: {entries in use, next slot,
  *                         training steps done, status flags}; flag bit 0 =
  *                         non-finite training input seen.
+ *  packed apsm_model_packed_bytes(M2, K, dict_cap) bytes: the same filter
+ *         re-laid out for the detection kernels (written by apsm_train and by
+ *         apsm_model_pack, read by apsm_detect).  Required when that size is
+ *         nonzero (2M <= 64 and K <= 8); may be NULL otherwise.  It does not
+ *         depend on sigma2.
  * sigma2 travels with the call (apsm_detect) rather than in this struct. */
 typedef struct apsm_model {
   int32_t M2;
@@ -110,12 +115,22 @@ typedef struct apsm_model {
   float* alpha;
   float* w;
   int32_t* state;
+  void* packed;
 } apsm_model_t;
 
+/* Size in bytes of apsm_model_t.packed for this shape; 0 if the shape needs
+ * no packed form.  Pure host function. */
+size_t apsm_model_packed_bytes(int M2, int K, int dict_cap);
+
+/* Rebuild model->packed from dict, alpha and state (e.g. after the caller
+ * wrote or modified the model arrays directly).  apsm_train does this
+ * itself.  Asynchronous on `stream`; no-op when the packed size is 0. */
+int apsm_model_pack(const apsm_model_t* model, void* stream);
+
 /* Training (Sec. II-D eqn:apsm with eqn:beta; Sec. III-B training phase).
- * Resets `model` to f_0 = 0 and runs the 2P steps n = 0..2P-1 of the real
+ * Resets `model` to f_0 = 0, runs the 2P steps n = 0..2P-1 of the real
  * training sequence r_{2t} = r1(t), r_{2t+1} = r2(t), b_{k,2t} = Re b_k(t),
- * b_{k,2t+1} = Im b_k(t).
+ * b_{k,2t+1} = Im b_k(t), and packs the result (apsm_model_pack).
  *  params     HOST, see apsm_params_t.
  *  M2         2M, even, 2..APSM_MAX_M2;  K  1..APSM_MAX_K;  P >= 1 pilots.
  *  rx_pilot   [P][M2] received pilot vectors (r1 layout).
@@ -127,6 +142,16 @@ typedef struct apsm_model {
 int apsm_train(const apsm_params_t* params, int M2, int K, int P,
                const float* rx_pilot, const float* sym_pilot,
                const apsm_model_t* model, void* stream);
+
+/* Training of n_inst detectors of one shape and one parameter set in one
+ * launch (one workgroup per detector, so they train concurrently).  Detector
+ * i reads rx_pilot + i*P*M2 and sym_pilot + i*P*K*2 (contiguous [n_inst][P][M2]
+ * and [n_inst][P][K][2] arrays) and writes models[i].
+ *  models     HOST array of n_inst model descriptors, each as for apsm_train.
+ * Same results as n_inst apsm_train calls; n_inst = 0 is a no-op. */
+int apsm_train_batched(const apsm_params_t* params, int M2, int K, int P, int n_inst,
+                       const float* rx_pilot, const float* sym_pilot,
+                       const apsm_model_t* models, void* stream);
 
 /* Detection (Sec. III-B): for every received vector r(s), s = 0..S-1,
  * g_k = f_k(r1) + i f_k(r2) with the frozen filter `model` (read only).

@@ -12,7 +12,7 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
-__all__ = ["Params", "Model", "train", "detect", "APSMError", "library", "LIB_PATH",
+__all__ = ["Params", "Model", "train", "train_batched", "detect", "APSMError", "library", "LIB_PATH",
            "MOD_NONE", "MOD_QPSK", "MOD_QAM16"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapsm.so")
@@ -41,7 +41,8 @@ class _CParams(ctypes.Structure):
 class _CModel(ctypes.Structure):
     _fields_ = [("M2", ctypes.c_int32), ("K", ctypes.c_int32), ("dict_cap", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("dict", ctypes.c_void_p),
-                ("alpha", ctypes.c_void_p), ("w", ctypes.c_void_p), ("state", ctypes.c_void_p)]
+                ("alpha", ctypes.c_void_p), ("w", ctypes.c_void_p), ("state", ctypes.c_void_p),
+                ("packed", ctypes.c_void_p)]
 
 
 _lib = None
@@ -59,10 +60,17 @@ def library() -> ctypes.CDLL:
         L.apsm_train.argtypes = [ctypes.POINTER(_CParams), i32, i32, i32, vp, vp,
                                  ctypes.POINTER(_CModel), vp]
         L.apsm_train.restype = i32
+        L.apsm_train_batched.argtypes = [ctypes.POINTER(_CParams), i32, i32, i32, i32, vp, vp,
+                                         ctypes.POINTER(_CModel), vp]
+        L.apsm_train_batched.restype = i32
         L.apsm_detect.argtypes = [ctypes.POINTER(_CModel), f32, i32, vp, vp, vp, i32, vp, vp, vp]
         L.apsm_detect.restype = i32
         L.apsm_get_status.argtypes = [ctypes.POINTER(_CModel), ctypes.POINTER(ctypes.c_int32)]
         L.apsm_get_status.restype = i32
+        L.apsm_model_packed_bytes.argtypes = [i32, i32, i32]
+        L.apsm_model_packed_bytes.restype = ctypes.c_size_t
+        L.apsm_model_pack.argtypes = [ctypes.POINTER(_CModel), vp]
+        L.apsm_model_pack.restype = i32
         L.apsm_strerror.argtypes = [i32]
         L.apsm_strerror.restype = ctypes.c_char_p
         L.apsm_last_hip_error.argtypes = []
@@ -133,10 +141,21 @@ class Model:
         self.alpha = torch.zeros((dict_cap, K), dtype=torch.float32, device=dev)
         self.w = torch.zeros((K, M2), dtype=torch.float32, device=dev)
         self.state = torch.zeros(4, dtype=torch.int32, device=dev)
+        nbytes = library().apsm_model_packed_bytes(self.M2, self.K, self.dict_cap)
+        self.packed = torch.zeros(nbytes, dtype=torch.uint8, device=dev) if nbytes else None
 
     def _c(self) -> _CModel:
         return _CModel(self.M2, self.K, self.dict_cap, 0, self.dict.data_ptr(),
-                       self.alpha.data_ptr(), self.w.data_ptr(), self.state.data_ptr())
+                       self.alpha.data_ptr(), self.w.data_ptr(), self.state.data_ptr(),
+                       self.packed.data_ptr() if self.packed is not None else None)
+
+    def pack(self, stream=None) -> "Model":
+        """Rebuild the packed form after writing dict/alpha/w/state directly."""
+        m = self._c()
+        rc = library().apsm_model_pack(ctypes.byref(m), _stream_handle(stream))
+        if rc:
+            raise APSMError(rc, "apsm_model_pack")
+        return self
 
     def status(self):
         out = (ctypes.c_int32 * 4)()
@@ -165,6 +184,30 @@ def train(rx_pilot, sym_pilot, params: Params, model: Optional[Model] = None, st
     if rc:
         raise APSMError(rc, "apsm_train")
     return model
+
+
+def train_batched(rx_pilot, sym_pilot, params: Params, models=None, stream=None):
+    """rx_pilot [n][P][M2], sym_pilot [n][P][K][2] float32 (device) -> list of n
+    Models, trained concurrently in one launch."""
+    torch = _torch()
+    n, P, M2 = rx_pilot.shape
+    K = sym_pilot.shape[2]
+    _check(rx_pilot, torch.float32, (n, P, M2), "rx_pilot")
+    _check(sym_pilot, torch.float32, (n, P, K, 2), "sym_pilot")
+    if models is None:
+        models = [Model(M2, K, params.dict_cap, rx_pilot.device, params.sigma2) for _ in range(n)]
+    if len(models) != n:
+        raise ValueError("need one model per instance")
+    for m in models:
+        m.sigma2 = float(params.sigma2)
+    p, keep = params._c()
+    arr = (_CModel * n)(*[m._c() for m in models]) if n else None
+    rc = library().apsm_train_batched(ctypes.byref(p), M2, K, P, n, rx_pilot.data_ptr(),
+                                      sym_pilot.data_ptr(), arr, _stream_handle(stream))
+    del keep
+    if rc:
+        raise APSMError(rc, "apsm_train_batched")
+    return models
 
 
 def detect(model: Model, rx, modulation="qpsk", truth=None, want_soft: bool = True,

@@ -25,6 +25,7 @@ int check_model(const apsm_model_t* m) {
   if (m->M2 < 2 || (m->M2 & 1) || m->K < 1 || m->dict_cap < 1) return APSM_ERR_SHAPE;
   if (m->M2 > APSM_MAX_M2 || m->K > APSM_MAX_K || m->dict_cap > APSM_MAX_DICT)
     return APSM_ERR_UNSUPPORTED;
+  if (!m->packed && apsm::packed_model_bytes(m->M2, m->K, m->dict_cap) > 0) return APSM_ERR_INVALID_ARG;
   return APSM_OK;
 }
 
@@ -47,10 +48,10 @@ const char* apsm_strerror(int code) {
 
 const char* apsm_last_hip_error(void) { return g_last_hip_error.c_str(); }
 
-int apsm_train(const apsm_params_t* p, int M2, int K, int P, const float* rx_pilot,
-               const float* sym_pilot, const apsm_model_t* model, void* stream) {
-  if (!p || !rx_pilot || !sym_pilot) return APSM_ERR_INVALID_ARG;
-  if (int rc = check_model(model)) return rc;
+namespace {
+
+int check_params(const apsm_params_t* p) {
+  if (!p) return APSM_ERR_INVALID_ARG;
   if (!finite_pos(p->sigma2) || !std::isfinite(p->eps) || p->eps < 0.0f) return APSM_ERR_INVALID_ARG;
   if (!(p->mu > 0.0f && p->mu < 2.0f)) return APSM_ERR_INVALID_ARG;
   if (!std::isfinite(p->w_lin) || !std::isfinite(p->w_gauss) || p->w_lin < 0.0f ||
@@ -59,18 +60,30 @@ int apsm_train(const apsm_params_t* p, int M2, int K, int P, const float* rx_pil
   if (p->reserved != 0 || p->window < 1) return APSM_ERR_INVALID_ARG;
   if (p->window > APSM_MAX_WINDOW) return APSM_ERR_UNSUPPORTED;
   if (p->dict_cap < p->window) return APSM_ERR_INVALID_ARG;
-  if (P < 1 || M2 < 2 || (M2 & 1) || K < 1) return APSM_ERR_SHAPE;
+  if (p->pos_weights) {
+    for (int i = 0; i < p->window; ++i)
+      if (!finite_pos(p->pos_weights[i])) return APSM_ERR_INVALID_ARG;
+  }
+  return APSM_OK;
+}
+
+// Shared by apsm_train and apsm_train_batched: every check happens before the
+// first launch.
+int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const float* rx_pilot,
+               const float* sym_pilot, const apsm_model_t* models, void* stream) {
+  if (int rc = check_params(p)) return rc;
+  if (!rx_pilot || !sym_pilot || !models) return APSM_ERR_INVALID_ARG;
+  if (P < 1 || M2 < 2 || (M2 & 1) || K < 1 || n_inst < 0) return APSM_ERR_SHAPE;
   if (M2 > APSM_MAX_M2 || K > APSM_MAX_K) return APSM_ERR_UNSUPPORTED;
-  if (model->M2 != M2 || model->K != K || model->dict_cap != p->dict_cap) return APSM_ERR_SHAPE;
   if ((long long)P * 2 > (long long)INT32_MAX / 2) return APSM_ERR_UNSUPPORTED;
+  for (int i = 0; i < n_inst; ++i) {
+    if (int rc = check_model(&models[i])) return rc;
+    if (models[i].M2 != M2 || models[i].K != K || models[i].dict_cap != p->dict_cap) return APSM_ERR_SHAPE;
+  }
 
   apsm::TrainArgs a{};
   a.rx = rx_pilot;
   a.sym = sym_pilot;
-  a.dict = model->dict;
-  a.alpha = model->alpha;
-  a.w = model->w;
-  a.state = model->state;
   a.P = P;
   a.M2 = M2;
   a.M = M2 / 2;
@@ -83,13 +96,57 @@ int apsm_train(const apsm_params_t* p, int M2, int K, int P, const float* rx_pil
   a.wl = p->w_lin;
   a.wg = p->w_gauss;
   for (int i = 0; i < APSM_MAX_WINDOW; ++i) a.omega[i] = 1.0f;
-  if (p->pos_weights) {
-    for (int i = 0; i < p->window; ++i) {
-      if (!finite_pos(p->pos_weights[i])) return APSM_ERR_INVALID_ARG;
-      a.omega[i] = p->pos_weights[i];
+  if (p->pos_weights)
+    for (int i = 0; i < p->window; ++i) a.omega[i] = p->pos_weights[i];
+
+  for (int b0 = 0; b0 < n_inst; b0 += apsm::kMaxTrainBatch) {
+    const int nb = n_inst - b0 < apsm::kMaxTrainBatch ? n_inst - b0 : apsm::kMaxTrainBatch;
+    a.rx = rx_pilot + (size_t)b0 * P * M2;
+    a.sym = sym_pilot + (size_t)b0 * P * K * 2;
+    a.n_inst = nb;
+    for (int i = 0; i < nb; ++i) {
+      a.dict[i] = models[b0 + i].dict;
+      a.alpha[i] = models[b0 + i].alpha;
+      a.w[i] = models[b0 + i].w;
+      a.state[i] = models[b0 + i].state;
     }
+    hipError_t e = apsm::launch_train(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_status(e);
   }
-  return hip_status(apsm::launch_train(a, (hipStream_t)stream));
+  for (int i = 0; i < n_inst; ++i) {
+    const apsm_model_t& m = models[i];
+    hipError_t e = apsm::launch_pack_model(m.dict, m.alpha, m.state, m.dict_cap, M2, K, m.packed,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return APSM_OK;
+}
+
+}  // namespace
+
+int apsm_train(const apsm_params_t* p, int M2, int K, int P, const float* rx_pilot,
+               const float* sym_pilot, const apsm_model_t* model, void* stream) {
+  if (!model) return APSM_ERR_INVALID_ARG;
+  return train_impl(p, M2, K, P, 1, rx_pilot, sym_pilot, model, stream);
+}
+
+int apsm_train_batched(const apsm_params_t* p, int M2, int K, int P, int n_inst, const float* rx_pilot,
+                       const float* sym_pilot, const apsm_model_t* models, void* stream) {
+  if (n_inst == 0) return APSM_OK;
+  return train_impl(p, M2, K, P, n_inst, rx_pilot, sym_pilot, models, stream);
+}
+
+size_t apsm_model_packed_bytes(int M2, int K, int dict_cap) {
+  if (M2 < 2 || (M2 & 1) || K < 1 || dict_cap < 1 || M2 > APSM_MAX_M2 || K > APSM_MAX_K ||
+      dict_cap > APSM_MAX_DICT)
+    return 0;
+  return apsm::packed_model_bytes(M2, K, dict_cap);
+}
+
+int apsm_model_pack(const apsm_model_t* model, void* stream) {
+  if (int rc = check_model(model)) return rc;
+  return hip_status(apsm::launch_pack_model(model->dict, model->alpha, model->state, model->dict_cap,
+                                            model->M2, model->K, model->packed, (hipStream_t)stream));
 }
 
 int apsm_detect(const apsm_model_t* model, float sigma2, int S, const float* rx, float* soft,
@@ -111,6 +168,7 @@ int apsm_detect(const apsm_model_t* model, float sigma2, int S, const float* rx,
   a.alpha = model->alpha;
   a.w = model->w;
   a.state = model->state;
+  a.packed = static_cast<const unsigned char*>(model->packed);
   a.rx = rx;
   a.soft = soft;
   a.hard = hard;

@@ -1,0 +1,318 @@
+// Detection with split-FP16 MFMA (Sec. III-B evaluation of the frozen filter)
+// for inputs 2M <= 64 and K <= 8 users.
+//
+// The sample x dictionary inner products run on v_mfma_f32_32x32x16_f16 with
+// each FP32 operand split into two FP16 parts, v = hi + lo, and the three
+// products hi*hi + lo*hi + hi*lo accumulated in FP32.  This keeps about 22
+// significant bits per product (the dropped lo*lo term is ~2^-22 relative),
+// and, unlike FP32 MFMA, these matrix instructions execute concurrently with
+// the VALU work of other waves (exp2 and the coefficient FMAs), which is the
+// binding pipe of this kernel.
+//
+// Both operands are scaled by powers of two only (so the splits are exact
+// re-scalings): the dictionary by 2^e_d, fixed when the model is packed, and
+// each sample row by its own 2^e_x, so that the largest component lands in
+// [2^12, 2^13) and the lo parts stay clear of FP16 subnormals.  With
+// acc = 2^(e_x+e_d) (x.d - ||x||^2 / 2) from the MFMA (the row term enters as
+// its C operand), the exponent argument is
+//   log2(kappa_G) = fma(acc, 2c 2^-(e_x+e_d), -c ||d||^2),  c = log2(e) / (2 sigma^2).
+//
+// Layout: samples are the MFMA rows (A operand), held in registers for the
+// whole dictionary sweep; dictionary entries are the columns (B operand),
+// streamed through LDS in chunks of 64 from the packed model with a plain
+// 16-byte copy that is prefetched one chunk ahead.  Accumulator element r of
+// lane l is sample row 8(r/4) + 4(l/32) + r%4 against dictionary column l%32,
+// so each lane needs the K coefficients of one dictionary entry per tile and
+// keeps 16 x K partial outputs; a reduce-scatter across the 32 columns at the
+// end leaves each lane with K/2 finished outputs of one real vector.
+#pragma once
+
+#include "apsm_internal.h"
+
+namespace apsm {
+namespace f16 {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kChunk = 64;                 // dictionary entries per LDS stage
+constexpr int kHeader = 64;                // packed-model header bytes
+
+template <int M2P, int K>
+struct Geo {
+  static constexpr int NB = M2P / 16;              // 16-deep blocks per segment
+  static constexpr int NSTEP = 3 * NB;             // [hi|lo|hi] x [hi|hi|lo]
+  static constexpr int BSTR = 2 * M2P + 8;         // packed row: d_hi | d_lo | pad (halves)
+  static constexpr int ROW_B = BSTR * 2;           // bytes; dwords = 4 (mod 8): conflict-free b128 reads
+  static constexpr int K4 = (K + 3) / 4 * 4;
+  static constexpr int CSTR = K4 + 4;              // per-entry floats: K4 coefficients, ||d||^2, pad
+  static constexpr int KE = K + (K & 1);           // even user count for the reduce-scatter
+  static constexpr int A_BYTES = kChunk * ROW_B;
+  static constexpr int C_BYTES = kChunk * CSTR * 4;
+  static constexpr int STAGE_BYTES = A_BYTES + C_BYTES;
+};
+
+__host__ __device__ inline int pad16(int m2) { return (m2 + 15) / 16 * 16; }
+__host__ __device__ inline int cap64_of(int cap) { return (cap + kChunk - 1) / kChunk * kChunk; }
+
+inline bool supported(int M2, int K) { return M2 <= 64 && K <= 8; }
+
+// Bytes of the packed model for a supported shape.
+inline size_t packed_bytes(int M2, int K, int cap) {
+  const int M2P = pad16(M2), K4 = (K + 3) / 4 * 4;
+  return kHeader + (size_t)cap64_of(cap) * ((2 * M2P + 8) * 2 + (K4 + 4) * 4);
+}
+
+__device__ __forceinline__ void split_f16(float v, _Float16& hi, _Float16& lo) {
+#pragma clang fp contract(off)
+  hi = (_Float16)v;
+  lo = (_Float16)(v - (float)hi);
+}
+
+// Power-of-two exponent e with 2^e * maxabs in [2^12, 2^13); 0 for zero input.
+__device__ __forceinline__ int scale_exp(float maxabs) {
+  if (!(maxabs > 0.0f)) return 0;
+  int ex;
+  frexpf(maxabs, &ex);
+  return 13 - ex;
+}
+
+hipError_t launch_pack(const float* dict, const float* alpha, const int32_t* state, int cap, int M2,
+                       int K, unsigned char* packed, hipStream_t stream);
+hipError_t launch_detect_f16_m16(const DetectArgs& a, const unsigned char* packed, hipStream_t stream);
+hipError_t launch_detect_f16_m32(const DetectArgs& a, const unsigned char* packed, hipStream_t stream);
+hipError_t launch_detect_f16_m64(const DetectArgs& a, const unsigned char* packed, hipStream_t stream);
+
+// Next chunk of the packed model, held in registers while the current chunk
+// is being computed.
+template <int M2P, int K>
+struct Prefetch {
+  using G = Geo<M2P, K>;
+  static constexpr int NA = (G::A_BYTES / 16 + kThreads - 1) / kThreads;
+  static constexpr int NC = (G::C_BYTES / 16 + kThreads - 1) / kThreads;
+  floatx4 ra[NA], rc[NC];
+  __device__ __forceinline__ void load(const unsigned char* packed, int cap64, int row0) {
+    const floatx4* srcA = reinterpret_cast<const floatx4*>(packed + kHeader + (size_t)row0 * G::ROW_B);
+    const floatx4* srcC = reinterpret_cast<const floatx4*>(packed + kHeader + (size_t)cap64 * G::ROW_B +
+                                                           (size_t)row0 * G::CSTR * 4);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < G::A_BYTES / 16) ra[u] = srcA[e];
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < G::C_BYTES / 16) rc[u] = srcC[e];
+    }
+  }
+  __device__ __forceinline__ void store(unsigned char* st) const {
+    floatx4* dA = reinterpret_cast<floatx4*>(st);
+    floatx4* dC = reinterpret_cast<floatx4*>(st + G::A_BYTES);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < G::A_BYTES / 16) dA[e] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < G::C_BYTES / 16) dC[e] = rc[u];
+    }
+  }
+};
+
+template <int M2P, int K>
+__global__ __launch_bounds__(kThreads, 2) void detect_f16_kernel(DetectArgs a, const unsigned char* packed) {
+  using G = Geo<M2P, K>;
+  constexpr int NSTEP = G::NSTEP, NB = G::NB, KE = G::KE, K4 = G::K4, CSTR = G::CSTR;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * G::STAGE_BYTES + K * M2P * 4];
+  __shared__ unsigned int werr[8];
+  float* wl = reinterpret_cast<float*>(lds + 2 * G::STAGE_BYTES);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int j = lane & 31, h = lane >> 5;
+  const int M2 = a.M2, M = a.M;
+  const int cap64 = cap64_of(a.cap);
+  int D = a.state[0];
+  D = D < 0 ? 0 : (D > a.cap ? a.cap : D);
+  const int e_d = reinterpret_cast<const int*>(packed)[0];
+
+  for (int e = tid; e < K * M2P; e += kThreads) {
+    const int k = e / M2P, m = e - k * M2P;
+    wl[e] = m < M2 ? a.w[k * M2 + m] : 0.0f;
+  }
+  if (tid < 8) werr[tid] = 0;
+
+  // ---- A fragments: row j of this wave's tile is sample s0 + j/2, part j%2
+  // (r1 for part 0, r2 = [Im; -Re] for part 1); this lane holds components
+  // 16 b + 8 h + v of it.
+  const int s0 = (blockIdx.x * kWaves + wave) * 16;
+  const int my_smp = s0 + (j >> 1), my_part = j & 1;
+  const bool my_valid = my_smp < a.S;
+  const float* x = a.rx + (size_t)(my_valid ? my_smp : 0) * M2;
+  float xv[M2P / 2];
+  float nrm = 0.0f, mx = 0.0f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int m = 16 * b + 8 * h + v;
+      int src = my_part == 0 ? m : (m < M ? m + M : m - M);
+      src = src < M2 ? src : M2 - 1;
+      const float sg = (my_valid && m < M2) ? ((my_part == 1 && m >= M) ? -1.0f : 1.0f) : 0.0f;
+      const float t = sg * x[src];
+      xv[8 * b + v] = t;
+      nrm = fmaf(t, t, nrm);
+      mx = fmaxf(mx, fabsf(t));
+    }
+  nrm += __shfl_xor(nrm, 32);
+  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  const int e_x = scale_exp(mx);
+  const float xsc = ldexpf(1.0f, e_x);
+  half8 afr[NSTEP];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      _Float16 hi, lo;
+      split_f16(xv[8 * b + v] * xsc, hi, lo);
+      afr[b][v] = hi;
+      afr[NB + b][v] = lo;
+      afr[2 * NB + b][v] = hi;
+    }
+  const float my_cinit = ldexpf(-0.5f * nrm, e_x + e_d);
+  const float my_desc = ldexpf(2.0f * a.c2, -(e_x + e_d));
+  floatx16 cinit;
+  float desc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int src = 8 * (r / 4) + 4 * h + (r % 4);
+    cinit[r] = __shfl(my_cinit, src);
+    desc[r] = __shfl(my_desc, src);
+  }
+
+  float acc_k[16][KE];
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+#pragma unroll
+    for (int k = 0; k < KE; ++k) acc_k[r][k] = 0.0f;
+
+  // ---- dictionary sweep
+  const int nchunks = (D + kChunk - 1) / kChunk;
+  Prefetch<M2P, K> pf;
+  if (nchunks > 0) {
+    pf.load(packed, cap64, 0);
+    pf.store(lds);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    if (c + 1 < nchunks) pf.load(packed, cap64, (c + 1) * kChunk);
+    const unsigned char* st = lds + (c & 1) * G::STAGE_BYTES;
+    const _Float16* dh = reinterpret_cast<const _Float16*>(st);
+    const float* co = reinterpret_cast<const float*>(st + G::A_BYTES);
+#pragma unroll 1
+    for (int ct = 0; ct < kChunk / 32; ++ct) {
+      const _Float16* brow = dh + (ct * 32 + j) * G::BSTR + 8 * h;
+      floatx16 acc = cinit;
+#pragma unroll
+      for (int s = 0; s < NSTEP; ++s) {
+        // B steps: d_hi blocks (paired with x_hi, then x_lo), then d_lo blocks
+        const int off = s < NB ? 16 * s : (s < 2 * NB ? 16 * (s - NB) : M2P + 16 * (s - 2 * NB));
+        const half8 bv = *reinterpret_cast<const half8*>(brow + off);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(afr[s], bv, acc, 0, 0, 0);
+      }
+      float cr[CSTR];
+      const float* cp = co + (ct * 32 + j) * CSTR;
+#pragma unroll
+      for (int q = 0; q < CSTR; q += 4) {
+        const floatx4 v4 = *reinterpret_cast<const floatx4*>(cp + q);
+        cr[q] = v4[0]; cr[q + 1] = v4[1]; cr[q + 2] = v4[2]; cr[q + 3] = v4[3];
+      }
+      const float coln = -a.c2 * cr[K4];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float kap = __builtin_amdgcn_exp2f(fmaf(acc[r], desc[r], coln));
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc_k[r][k] = fmaf(cr[k], kap, acc_k[r][k]);
+      }
+    }
+    if (c + 1 < nchunks) pf.store(lds + ((c + 1) & 1) * G::STAGE_BYTES);
+    __syncthreads();
+  }
+
+  // ---- reduce-scatter over the 32 dictionary columns of each wave half
+  float v[16 * KE];
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+#pragma unroll
+    for (int k = 0; k < KE; ++k) v[r * KE + k] = acc_k[r][k];
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    const int half = (16 * KE) >> (t + 1);
+    const int mask = 16 >> t;
+    const bool upper = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const float send = upper ? v[i] : v[half + i];
+      const float keep = upper ? v[half + i] : v[i];
+      v[i] = keep + __shfl_xor(send, mask);
+    }
+  }
+  // Lane (j, h) now holds accumulator row r = j/2 (sample row
+  // 8(r/4) + 4h + r%4) for users k0 .. k0 + KE/2 - 1, k0 = (j%2) KE/2.
+  const int r = j >> 1;
+  const int rho = 8 * (r >> 2) + 4 * h + (r & 3);
+  const int smp = s0 + (rho >> 1), part = rho & 1;
+  const bool valid = smp < a.S;
+  const int k0 = (j & 1) * (KE / 2);
+  const float* xr = a.rx + (size_t)(valid ? smp : 0) * M2;
+  float lin[KE / 2];
+#pragma unroll
+  for (int u = 0; u < KE / 2; ++u) lin[u] = 0.0f;
+  for (int m = 0; m < M2; ++m) {
+    const int src = part == 0 ? m : (m < M ? m + M : m - M);
+    const float xvm = (part == 1 && m >= M) ? -xr[src] : xr[src];
+#pragma unroll
+    for (int u = 0; u < KE / 2; ++u) {
+      const int k = k0 + u < K ? k0 + u : K - 1;
+      lin[u] = fmaf(wl[k * M2P + m], xvm, lin[u]);
+    }
+  }
+  const int bits = a.modulation >> 1;              // per axis: 1 (QPSK) or 2 (16-QAM)
+  const bool has_err = a.err != nullptr;
+#pragma unroll
+  for (int u = 0; u < KE / 2; ++u) {
+    const int k = k0 + u;
+    const bool kval = k < K;
+    const float val = v[u] + lin[u];
+    if (a.soft && valid && kval) a.soft[((size_t)smp * a.K + k) * 2 + part] = val;
+    if (a.modulation) {
+      int idx;
+      if (bits == 1) {
+        idx = val >= 0.0f ? 1 : 0;
+      } else {
+        const float th = 0.63245553203367586640f;  // 2 / sqrt(10)
+        idx = (val >= -th) + (val >= 0.0f) + (val >= th);
+      }
+      const int gr = idx ^ (idx >> 1);
+      const int other = __shfl_xor(gr, 2);         // the lane holding the other part of this sample
+      const int label = part == 0 ? ((gr << bits) | other) : ((other << bits) | gr);
+      if (part == 0 && valid && kval) {
+        if (a.hard) a.hard[(size_t)smp * a.K + k] = (uint8_t)label;
+        if (has_err && label != a.truth[(size_t)smp * a.K + k]) atomicAdd(&werr[k], 1u);
+      }
+    }
+  }
+  if (has_err) {
+    __syncthreads();
+    if (tid < K && werr[tid]) atomicAdd(a.err + tid, (unsigned long long)werr[tid]);
+  }
+}
+
+}  // namespace f16
+}  // namespace apsm

@@ -210,9 +210,9 @@ __global__ __launch_bounds__(kThreads, min_waves<M2P>()) void detect_kernel(Dete
   // ---- linear part, sum of the two wave halves, outputs
   const bool has_err = a.err != nullptr;
   const int bits = a.modulation >> 1;                 // per axis: 1 (QPSK) or 2 (16-QAM)
-  int nerr[K];                                         // wave-uniform counts
-#pragma unroll
-  for (int k = 0; k < K; ++k) nerr[k] = 0;
+  __shared__ unsigned int werr[K];                    // workgroup error counts
+  if (tid < K) werr[tid] = 0;
+  __syncthreads();
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const bool valid = smp[nt] < a.S;
@@ -236,19 +236,16 @@ __global__ __launch_bounds__(kThreads, min_waves<M2P>()) void detect_kernel(Dete
         const int gr = idx ^ (idx >> 1);
         const int other = __shfl_xor(gr, 1);
         const int label = part == 0 ? ((gr << bits) | other) : ((other << bits) | gr);
-        bool wrong = false;
         if (part == 0 && valid && (k & 1) == h) {
           if (a.hard) a.hard[(size_t)smp[nt] * a.K + k] = (uint8_t)label;
-          if (has_err) wrong = label != a.truth[(size_t)smp[nt] * a.K + k];
+          if (has_err && label != a.truth[(size_t)smp[nt] * a.K + k]) atomicAdd(&werr[k], 1u);
         }
-        if (has_err) nerr[k] += __popcll(__ballot(wrong));
       }
     }
   }
   if (has_err) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (nerr[k] && lane == 0) atomicAdd(a.err + k, (unsigned long long)nerr[k]);
+    __syncthreads();
+    if (tid < K && werr[tid]) atomicAdd(a.err + tid, (unsigned long long)werr[tid]);
   }
 }
 
@@ -261,17 +258,24 @@ hipError_t launch_mk(const DetectArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// The FP32 path serves 2M > 64 (every K) and K > 8 (every 2M); smaller
+// shapes take the split-FP16 kernels.
 template <int M2P>
 hipError_t launch_m(const DetectArgs& a, hipStream_t stream) {
+  if constexpr (M2P > 64) {
+    switch (a.K) {
+      case 1: return launch_mk<M2P, 1>(a, stream);
+      case 2: return launch_mk<M2P, 2>(a, stream);
+      case 3: return launch_mk<M2P, 3>(a, stream);
+      case 4: return launch_mk<M2P, 4>(a, stream);
+      case 5: return launch_mk<M2P, 5>(a, stream);
+      case 6: return launch_mk<M2P, 6>(a, stream);
+      case 7: return launch_mk<M2P, 7>(a, stream);
+      case 8: return launch_mk<M2P, 8>(a, stream);
+      default: break;
+    }
+  }
   switch (a.K) {
-    case 1: return launch_mk<M2P, 1>(a, stream);
-    case 2: return launch_mk<M2P, 2>(a, stream);
-    case 3: return launch_mk<M2P, 3>(a, stream);
-    case 4: return launch_mk<M2P, 4>(a, stream);
-    case 5: return launch_mk<M2P, 5>(a, stream);
-    case 6: return launch_mk<M2P, 6>(a, stream);
-    case 7: return launch_mk<M2P, 7>(a, stream);
-    case 8: return launch_mk<M2P, 8>(a, stream);
     case 9: return launch_mk<M2P, 9>(a, stream);
     case 10: return launch_mk<M2P, 10>(a, stream);
     case 11: return launch_mk<M2P, 11>(a, stream);

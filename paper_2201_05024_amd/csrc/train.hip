@@ -37,15 +37,32 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-// Sum over the 64 lanes of a wave; the result is valid in lane 63.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x140, 0xF, 0xF, false);  // row_mirror
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
-  return v;
+// Reduce-scatter of KP per-lane values over the 64 lanes of a wave: returns,
+// in every lane L, the wave sum of value number L >> (6 - log2 KP).  Costs
+// KP - 1 + 6 - log2(KP) lane exchanges instead of 6 KP for KP full sums.
+template <int KP>
+__device__ __forceinline__ float wave_reduce_scatter(const float (&in)[KP]) {
+  constexpr int LOG = KP == 1 ? 0 : KP == 2 ? 1 : KP == 4 ? 2 : KP == 8 ? 3 : 4;
+  float v[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) v[i] = in[i];
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < LOG; ++t) {
+    const int half = KP >> (t + 1);
+    const int mask = 32 >> t;
+    const bool upper = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const float send = upper ? v[i] : v[half + i];
+      const float keep = upper ? v[half + i] : v[i];
+      v[i] = keep + __shfl_xor(send, mask);
+    }
+  }
+  float r = v[0];
+#pragma unroll
+  for (int t = LOG; t < 6; ++t) r += __shfl_xor(r, 32 >> t);
+  return r;
 }
 
 __device__ __forceinline__ float soft_threshold(float x, float eps) {
@@ -136,6 +153,13 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   const int EVS = W > 1 ? W - 1 : 1;
   const int KM = K * M2;
   Lds s = carve(lds_raw, W, KP, M2P);
+  const int inst = blockIdx.x;
+  const float* rx = a.rx + (size_t)inst * a.P * M2;
+  const float* sym = a.sym + (size_t)inst * a.P * K * 2;
+  float* const dict = a.dict[inst];
+  float* const alpha = a.alpha[inst];
+  float* const wout = a.w[inst];
+  int32_t* const state = a.state[inst];
 
   for (int i = tid; i < W * KP; i += kThreads) {
     s.e[i] = 0.0f;
@@ -178,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     }
   } else {
     // Model buffers hold the dictionary; start from an empty one.
-    for (size_t i = tid; i < (size_t)cap * K; i += kThreads) a.alpha[i] = 0.0f;
+    for (size_t i = tid; i < (size_t)cap * K; i += kThreads) alpha[i] = 0.0f;
   }
   __shared__ int block_flags;
   if (tid == 0) block_flags = 0;
@@ -189,18 +213,18 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   // phase C) and b_{k,n+1} for thread k.
   float comp_nx = 0.0f, bv = 0.0f, bv_nx = 0.0f;
   if (tid < M2P) {
-    const float c0 = sample_comp(a.rx, M2, M, 0, tid);
+    const float c0 = sample_comp(rx, M2, M, 0, tid);
     s.rwin[tid] = c0;
     s.rwin[R * M2P + tid] = c0;
   }
-  bv = tid < K ? a.sym[tid * 2] : 0.0f;
+  bv = tid < K ? sym[tid * 2] : 0.0f;
   __syncthreads();
 
   int sn = 0, nw = 0, nr = 0;               // n % cap, n % W, n % R
   for (int n = 0; n < T; ++n) {
     if (n + 1 < T) {
-      comp_nx = tid < M2P ? sample_comp(a.rx, M2, M, n + 1, tid) : 0.0f;
-      bv_nx = tid < K ? a.sym[((size_t)((n + 1) >> 1) * K + tid) * 2 + ((n + 1) & 1)] : 0.0f;
+      comp_nx = tid < M2P ? sample_comp(rx, M2, M, n + 1, tid) : 0.0f;
+      bv_nx = tid < K ? sym[((size_t)((n + 1) >> 1) * K + tid) * 2 + ((n + 1) & 1)] : 0.0f;
     }
 
     // ------------------------------------------------------------ phase A
@@ -249,9 +273,10 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
         }
         if (slot < cap && slot <= n) {
           const int back = ring_sub(sn, slot, cap);   // this slot holds sample n - back
-          float dot = 0.0f;
+          float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-          for (int m = 0; m < M2P; ++m) dot = fmaf(rn[m], dreg[u][m], dot);
+          for (int m = 0; m < M2P; ++m) d4[m & 3] = fmaf(rn[m], dreg[u][m], d4[m & 3]);
+          const float dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
           const float kg = __builtin_amdgcn_exp2f(a.c2 * (2.0f * dot - nn - dnorm[u]));
 #pragma unroll
           for (int k = 0; k < KP; ++k) part[k] = fmaf(areg[u][k], kg, part[k]);
@@ -269,8 +294,8 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
       }
     } else {
       for (int slot = tid; slot < cap && slot <= n; slot += kThreads) {
-        float* drow = a.dict + (size_t)slot * M2;
-        float* arow = a.alpha + (size_t)slot * K;
+        float* drow = dict + (size_t)slot * M2;
+        float* arow = alpha + (size_t)slot * K;
         if (slot == sn) {
           if (evicting) {
             for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
@@ -301,10 +326,10 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
         if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
       }
     }
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const float v = wave_sum_to_last(part[k]);
-      if (lane == 63) s.part[wave * KP + k] = v;
+    {
+      constexpr int SH = KP == 1 ? 6 : KP == 2 ? 5 : KP == 4 ? 4 : KP == 8 ? 3 : 2;
+      const float v = wave_reduce_scatter<KP>(part);
+      if ((lane & ((1 << SH) - 1)) == 0) s.part[wave * KP + (lane >> SH)] = v;
     }
     __syncthreads();
 
@@ -343,7 +368,33 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
 
     // ------------------------------------------------------------ phase D
     const float* cbase = s.c + (nw + W) * KP;       // member n - q at cbase - q * KP
-    for (int t = tid; t < L * KP; t += kThreads) {
+    {
+      // This thread's first prediction update and first linear coefficient
+      // share one sweep over the window (more loads in flight per round).
+      const int t = tid;
+      const bool has_e = t < L * KP && (t % KP) < K;
+      const bool has_w = wk[0] < KP;
+      const int ep = has_e ? t / KP : 0, ek = has_e ? t % KP : 0;
+      const float* ce = cbase + ek;
+      const float* ge = s.gram + (nr + R) * R + ring_sub(nr, ep, R);
+      const float* cw = cbase + (has_w ? wk[0] : 0);
+      const float* rw = s.rwin + (nr + R) * M2P + wm[0];
+      float e0 = 0.0f, e1 = 0.0f, w0 = 0.0f, w1 = 0.0f;
+      int q = 0;
+      for (; q + 2 <= L; q += 2) {
+        e0 = fmaf(ce[-q * KP], ge[-q * R], e0);
+        w0 = fmaf(cw[-q * KP], rw[-q * M2P], w0);
+        e1 = fmaf(ce[-(q + 1) * KP], ge[-(q + 1) * R], e1);
+        w1 = fmaf(cw[-(q + 1) * KP], rw[-(q + 1) * M2P], w1);
+      }
+      if (q < L) {
+        e0 = fmaf(ce[-q * KP], ge[-q * R], e0);
+        w0 = fmaf(cw[-q * KP], rw[-q * M2P], w0);
+      }
+      if (has_e) s.e[ring_sub(nw, ep, W) * KP + ek] += e0 + e1;
+      if (has_w) wreg[0] = fmaf(a.wl, w0 + w1, wreg[0]);
+    }
+    for (int t = tid + kThreads; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
       if (k >= K) continue;
       const int ir = ring_sub(nr, p, R);
@@ -370,12 +421,12 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
         const int slot = ring_sub(sn, q, cap);
         if ((slot & (kThreads - 1)) != tid) continue;
         const float* cj = cbase - q * KP;
-        float* arow = a.alpha + (size_t)slot * K;
+        float* arow = alpha + (size_t)slot * K;
         for (int k = 0; k < K; ++k) arow[k] = fmaf(cj[k], a.wg, arow[k]);
       }
     }
 #pragma unroll
-    for (int u = 0; u < WPT; ++u) {
+    for (int u = 1; u < WPT; ++u) {
       if (wk[u] >= KP) continue;
       const float acc = sweep(cbase + wk[u], KP, s.rwin + (nr + R) * M2P + wm[u], M2P, L);
       wreg[u] = fmaf(a.wl, acc, wreg[u]);
@@ -397,11 +448,11 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     for (int u = 0; u < SLOTS; ++u) {
       const int slot = tid + kThreads * u;
       if (slot < cap) {
-        float* drow = a.dict + (size_t)slot * M2;
+        float* drow = dict + (size_t)slot * M2;
 #pragma unroll
         for (int mm = 0; mm < M2P; ++mm)
           if (mm < M2) drow[mm] = dreg[u][mm];
-        float* arow = a.alpha + (size_t)slot * K;
+        float* arow = alpha + (size_t)slot * K;
 #pragma unroll
         for (int k = 0; k < KP; ++k)
           if (k < K) arow[k] = areg[u][k];
@@ -409,18 +460,18 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     }
   } else {
     // Slots never written (T < cap) are cleared so detection may sum them.
-    for (size_t i = (size_t)T * M2 + tid; i < (size_t)cap * M2; i += kThreads) a.dict[i] = 0.0f;
+    for (size_t i = (size_t)T * M2 + tid; i < (size_t)cap * M2; i += kThreads) dict[i] = 0.0f;
   }
 #pragma unroll
   for (int u = 0; u < WPT; ++u)
-    if (wk[u] < KP) a.w[tid + kThreads * u] = wreg[u];
+    if (wk[u] < KP) wout[tid + kThreads * u] = wreg[u];
   if (flags) atomicOr(&block_flags, flags);
   __syncthreads();
   if (tid == 0) {
-    a.state[0] = T < cap ? T : cap;
-    a.state[1] = T % cap;
-    a.state[2] = T;
-    a.state[3] = block_flags;
+    state[0] = T < cap ? T : cap;
+    state[1] = T % cap;
+    state[2] = T;
+    state[3] = block_flags;
   }
 }
 
@@ -431,7 +482,7 @@ hipError_t launch_one(const TrainArgs& a, hipStream_t stream) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(1), dim3(kThreads), bytes, stream, a);
+  hipLaunchKernelGGL(kern, dim3(a.n_inst), dim3(kThreads), bytes, stream, a);
   return hipGetLastError();
 }
 

@@ -43,8 +43,8 @@ def test_strerror_and_version():
         assert isinstance(L.apsm_strerror(code), bytes) and L.apsm_strerror(code)
 
 
-def _model(M2=32, K=6, cap=256, ptr=1):
-    return A._CModel(M2, K, cap, 0, ptr, ptr, ptr, ptr)
+def _model(M2=32, K=6, cap=256, ptr=1, packed=1):
+    return A._CModel(M2, K, cap, 0, ptr, ptr, ptr, ptr, packed)
 
 
 def _params(**kw):
@@ -111,5 +111,18 @@ def test_detect_rejects_bad_args():
     assert call(rx=None) == 1
     assert call(model=_model(M2=7)) == 2
     assert call(model=_model(K=0)) == 2
+    assert call(model=_model(packed=None)) == 1         # this shape needs the packed form
+    assert call(model=_model(M2=128, K=6, packed=None), S=0) == 0   # ... this one does not
     assert call(S=0) == 0                               # empty input: nothing launched
     assert call(S=0, rx=None, soft=None) == 0           # ... and no buffers needed
+
+
+@needs_lib
+def test_packed_bytes():
+    L = A.library()
+    L.apsm_model_packed_bytes.restype = ctypes.c_size_t
+    # 2M = 32 -> rows of (2*32 + 8) halves, K = 6 -> (8 + 4) floats per entry, cap 1000 -> 1024 rows
+    assert L.apsm_model_packed_bytes(32, 6, 1000) == 64 + 1024 * (72 * 2 + 12 * 4)
+    assert L.apsm_model_packed_bytes(128, 16, 1000) == 0      # detected without a packed form
+    assert L.apsm_model_packed_bytes(33, 6, 10) == 0          # invalid shape
+    assert L.apsm_model_pack(None, None) == 1

@@ -36,6 +36,7 @@ def test_detect_golden_two_entries():
     m.alpha.copy_(cuda(np.array(fx["alpha"], dtype=np.float32)))
     m.w.copy_(cuda(np.array(fx["w"], dtype=np.float32)))
     m.state.copy_(cuda(np.array([2, 0, 2, 0], dtype=np.int32)))
+    m.pack()
     out = A.detect(m, cuda(np.array(fx["rx"], dtype=np.float32)), modulation=None)
     np.testing.assert_allclose(out["soft"].cpu().numpy(), fx["expected_soft"], atol=2e-6)
 
@@ -66,6 +67,7 @@ def test_detect_only_parity(K, M, P, S, cap, W, mod):
     m.alpha.copy_(cuda(al.astype(np.float32)))
     m.w.copy_(cuda(f.w.astype(np.float32)))
     m.state.copy_(cuda(np.array([len(f.dict_vec), 0, 2 * P, 0], dtype=np.int32)))
+    m.pack()
     out = A.detect(m, cuda(inst.rx_data), modulation=mod, truth=cuda(inst.truth))
     torch.cuda.synchronize()
     soft_ref = O.detect_planar(f, inst.rx_data)
@@ -241,3 +243,19 @@ def test_nonfinite_training_input_flagged():
     assert m.status()["flags"] & 1
     m2 = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), A.Params(window=4, dict_cap=40), model=m)
     assert m2.status()["flags"] == 0
+
+
+def test_batched_training_equals_single():
+    """apsm_train_batched gives bit-identical models to per-instance training
+    (and more instances than one launch holds are split correctly)."""
+    specs = [synth.InstanceSpec(K=3, M=4, P=50, S=64, snr_db=8.0 + i, seed=300 + i) for i in range(35)]
+    insts = [synth.make_instance(sp) for sp in specs]
+    p = A.Params(window=6, dict_cap=64)
+    rx = cuda(np.stack([i.rx_pilot for i in insts]))
+    sym = cuda(np.stack([i.sym_pilot for i in insts]))
+    models = A.train_batched(rx, sym, p)
+    for idx in (0, 17, 31, 32, 34):
+        single = A.train(cuda(insts[idx].rx_pilot), cuda(insts[idx].sym_pilot), p)
+        torch.cuda.synchronize()
+        for name in ("dict", "alpha", "w", "state", "packed"):
+            assert torch.equal(getattr(models[idx], name), getattr(single, name)), (idx, name)
