@@ -47,6 +47,9 @@ def parse():
                     help="skip the oracle timing (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched mixed-shape workload")
+    ap.add_argument("--batched-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -82,6 +85,99 @@ def cpu_baseline(spec_fn, snr, params, S_full, n_inst):
         "sample": (f"FP64 oracle, 1 thread: full training of one {snr:g} dB instance "
                    f"({t_train:.2f} s) and detection of 1024 of {S_full} data symbols "
                    f"({t_det:.2f} s), extrapolated linearly to {n_inst} instances x {S_full} symbols"),
+    }
+
+
+def run_batched(args, dev):
+    """The batched mixed-shape workload: 256 detectors (K 2..8, 8/16/32
+    antennas, dictionaries of 64..2048 entries with as many pilots, 65,536
+    received vectors each, QPSK/16-QAM mixed) trained in one launch and
+    detected in one launch, against the plain form (one apsm_train and one
+    apsm_detect launch per detector) on the same buffers."""
+    import torch
+    import synth
+    import paper_2201_05024_amd as A
+
+    n = synth.BATCH_INSTANCES
+    log(f"[bench] generating the batched workload ({n} detectors)")
+    params = A.Params(eps=0.05, mu=1.0, window=32)
+    items, evals, syms, flops = [], 0, 0, 0
+    for i in range(n):
+        spec, D = synth.spec_batch_mixed(i)
+        inst = synth.make_instance(spec)
+        K, M2, S = spec.K, 2 * spec.M, spec.S
+        items.append(A.BatchItem(
+            model=A.Model(M2, K, D, dev, 0.5), rx_pilot=torch.from_numpy(inst.rx_pilot).to(dev),
+            sym_pilot=torch.from_numpy(inst.sym_pilot).to(dev), rx=torch.from_numpy(inst.rx_data).to(dev),
+            modulation=spec.modulation, soft=torch.empty((S, K, 2), dtype=torch.float32, device=dev),
+            hard=torch.empty((S, K), dtype=torch.uint8, device=dev),
+            truth=torch.from_numpy(inst.truth).to(dev), errors=torch.zeros(K, dtype=torch.int64, device=dev),
+            sigma2=0.5))
+        evals += 2 * S * D
+        flops += 2 * S * D * (2 + 8 + 2 * K)
+        syms += S * K
+    batch = A.Batch(params, items)
+    stream = torch.cuda.current_stream()
+    batch.train(stream).detect(stream)
+    batch.tune(stream)
+    torch.cuda.synchronize()
+
+    def batched_step():
+        for it in items:
+            it.errors.zero_()
+        batch.train(stream).detect(stream)
+
+    def plain_step():
+        for it in items:
+            it.errors.zero_()
+            p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, dict_cap=it.model.dict_cap)
+            A.train(it.rx_pilot, it.sym_pilot, p, model=it.model, stream=stream)
+            A.detect(it.model, it.rx, modulation=it.modulation, truth=it.truth, soft=it.soft, hard=it.hard,
+                     errors=it.errors, stream=stream)
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    log("[bench] batched form")
+    t_batched = timed(batched_step, args.batched_steps)
+    log("[bench] plain form")
+    t_plain = timed(plain_step, 2)
+    # the detection launch alone, with HIP events on its stream
+    ev = []
+    for _ in range(args.batched_steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        batch.detect(stream)
+        e1.record(stream)
+        ev.append((e0, e1))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    batch.train(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    det_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+    train_ms = e0.elapsed_time(e1)
+    achieved = flops / det_s / 1e12
+    return {
+        "workload": (f"{n} detectors, K 2..8, 8/16/32 antennas, dictionaries 64..2048 (= pilots), "
+                     "65536 vectors each, QPSK/16-QAM mixed, SNR 5..20 dB, W=32, sigma2=0.5"),
+        "batched_user_symbols_per_s": syms / t_batched,
+        "plain_user_symbols_per_s": syms / t_plain,
+        "speedup_vs_plain": t_plain / t_batched,
+        "ms_per_step_batched": t_batched * 1e3,
+        "ms_per_step_plain": t_plain * 1e3,
+        "train_ms_one_launch": train_ms,
+        "detect_ms_one_launch": det_s * 1e3,
+        "kernel_evals_per_s": evals / det_s,
+        "roofline": {"kernel": "detect_batch_kernel", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None},
     }
 
 
@@ -223,6 +319,8 @@ def main():
         log("[bench] timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(lambda snr, S: synth.spec_slot(snr, S=S), 10.0, params,
                                            S, n_inst)
+    if not args.no_batched:
+        out["batched"] = run_batched(args, dev)
     if args.copy_calibration:
         n = 64 << 20
         a = torch.ones(n, dtype=torch.float32, device=dev)

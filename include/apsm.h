@@ -170,6 +170,80 @@ int apsm_detect(const apsm_model_t* model, float sigma2, int S,
                 const float* rx, float* soft, uint8_t* hard, int modulation,
                 const uint8_t* truth, int64_t* err_count, void* stream);
 
+/* ---- batches of detectors with different shapes ----------------------
+ * Many independent detectors (each its own user count K, input dimension
+ * M2, pilot count, dictionary capacity, sigma^2, data size and modulation)
+ * trained in one launch and detected in one launch, so that a batch of small
+ * problems fills the GPU and its whole train -> detect -> error-count
+ * sequence can be captured once in a HIP graph and replayed.  Each detector
+ * gives exactly the results that apsm_train and apsm_detect give for it
+ * alone.  Use:
+ *   apsm_batch_create      describe the detectors (host only),
+ *   apsm_batch_workspace_bytes / apsm_batch_bind
+ *                          give the batch its device tables (caller-owned
+ *                          workspace, written once, synchronously),
+ *   apsm_batch_tune        optional: time the launch forms on this batch and
+ *                          keep the fastest (synchronous; not while capturing),
+ *   apsm_batch_train, apsm_batch_detect
+ *                          asynchronous launches on `stream`, no allocation,
+ *                          no host synchronisation (capturable),
+ *   apsm_batch_destroy.
+ * The buffers named in the items must stay valid while the batch is used. */
+typedef struct apsm_batch_item {
+  apsm_model_t model;          /* shape (M2, K, dict_cap) and arrays of this detector   */
+  float sigma2;                /* its kernel width (> 0)                                 */
+  int32_t P;                   /* pilots, >= 1 (training)                               */
+  const float* rx_pilot;       /* [P][M2]                                                */
+  const float* sym_pilot;      /* [P][K][2]                                              */
+  int32_t S;                   /* received vectors to detect, >= 0                      */
+  int32_t modulation;          /* APSM_MOD_*                                             */
+  const float* rx;             /* [S][M2]                                                */
+  float* soft;                 /* [S][K][2] or NULL                                      */
+  uint8_t* hard;               /* [S][K] or NULL (needs modulation != NONE)              */
+  const uint8_t* truth;        /* [S][K] or NULL                                         */
+  int64_t* err_count;          /* [K], added to; NULL iff truth is NULL                  */
+} apsm_batch_item_t;
+
+typedef struct apsm_batch apsm_batch_t;   /* opaque host object */
+
+/* Validate and describe n >= 1 detectors.  params (HOST) gives eps, mu, w_lin,
+ * w_gauss, window and pos_weights shared by all of them; its sigma2 and
+ * dict_cap are not used (each item has its own).  Every item must satisfy
+ * what apsm_train and apsm_detect require of the same arguments, and
+ * model.dict_cap >= window.  On success *out is a new batch. */
+int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* items, int n,
+                      apsm_batch_t** out);
+
+/* Bytes of device workspace the batch needs (job tables, the work-item list
+ * of detection and two claim counters). */
+size_t apsm_batch_workspace_bytes(const apsm_batch_t* batch);
+
+/* Write the batch's tables into `workspace` (DEVICE, at least
+ * apsm_batch_workspace_bytes, 256-byte aligned, caller-owned; it must not be
+ * used for anything else while the batch is used).  Synchronous: returns
+ * after the copy on `stream` has completed. */
+int apsm_batch_bind(apsm_batch_t* batch, void* workspace, size_t bytes, void* stream);
+
+/* Time the launch forms of batched detection on this batch (persistent
+ * workgroups claiming tiles from a counter, or one workgroup per tile) and
+ * keep the faster one for this batch and for later batches of the same
+ * shape mix (the choice is cached per process).  Runs the batch's detection
+ * several times: soft and hard outputs are overwritten and err_count
+ * accumulates those runs, so zero err_count afterwards.  Synchronous. */
+int apsm_batch_tune(apsm_batch_t* batch, void* stream);
+
+/* Train every detector of the batch (same results as apsm_train per item)
+ * and pack the models; asynchronous on `stream`. */
+int apsm_batch_train(const apsm_batch_t* batch, void* stream);
+
+/* Detect every item's received vectors (same results as apsm_detect per
+ * item); asynchronous on `stream`.  Calls of one batch must not overlap
+ * (they share the claim counters in the workspace). */
+int apsm_batch_detect(const apsm_batch_t* batch, void* stream);
+
+/* Release the host object (not the workspace).  NULL is allowed. */
+void apsm_batch_destroy(apsm_batch_t* batch);
+
 /* Synchronous copy of model->state into host_state[4]; waits for all work on
  * the device. */
 int apsm_get_status(const apsm_model_t* model, int32_t* host_state);

@@ -12,8 +12,8 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
-__all__ = ["Params", "Model", "train", "train_batched", "detect", "APSMError", "library", "LIB_PATH",
-           "MOD_NONE", "MOD_QPSK", "MOD_QAM16"]
+__all__ = ["Params", "Model", "train", "train_batched", "detect", "Batch", "BatchItem", "APSMError",
+           "library", "LIB_PATH", "MOD_NONE", "MOD_QPSK", "MOD_QAM16"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapsm.so")
 
@@ -45,6 +45,14 @@ class _CModel(ctypes.Structure):
                 ("packed", ctypes.c_void_p)]
 
 
+class _CBatchItem(ctypes.Structure):
+    _fields_ = [("model", _CModel), ("sigma2", ctypes.c_float), ("P", ctypes.c_int32),
+                ("rx_pilot", ctypes.c_void_p), ("sym_pilot", ctypes.c_void_p),
+                ("S", ctypes.c_int32), ("modulation", ctypes.c_int32), ("rx", ctypes.c_void_p),
+                ("soft", ctypes.c_void_p), ("hard", ctypes.c_void_p), ("truth", ctypes.c_void_p),
+                ("err_count", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -71,6 +79,21 @@ def library() -> ctypes.CDLL:
         L.apsm_model_packed_bytes.restype = ctypes.c_size_t
         L.apsm_model_pack.argtypes = [ctypes.POINTER(_CModel), vp]
         L.apsm_model_pack.restype = i32
+        L.apsm_batch_create.argtypes = [ctypes.POINTER(_CParams), ctypes.POINTER(_CBatchItem), i32,
+                                        ctypes.POINTER(vp)]
+        L.apsm_batch_create.restype = i32
+        L.apsm_batch_workspace_bytes.argtypes = [vp]
+        L.apsm_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.apsm_batch_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.apsm_batch_bind.restype = i32
+        L.apsm_batch_tune.argtypes = [vp, vp]
+        L.apsm_batch_tune.restype = i32
+        L.apsm_batch_train.argtypes = [vp, vp]
+        L.apsm_batch_train.restype = i32
+        L.apsm_batch_detect.argtypes = [vp, vp]
+        L.apsm_batch_detect.restype = i32
+        L.apsm_batch_destroy.argtypes = [vp]
+        L.apsm_batch_destroy.restype = None
         L.apsm_strerror.argtypes = [i32]
         L.apsm_strerror.restype = ctypes.c_char_p
         L.apsm_last_hip_error.argtypes = []
@@ -244,3 +267,109 @@ def detect(model: Model, rx, modulation="qpsk", truth=None, want_soft: bool = Tr
     if rc:
         raise APSMError(rc, "apsm_detect")
     return {"soft": soft, "hard": hard, "errors": errors}
+
+
+@dataclass
+class BatchItem:
+    """One detector of a Batch: its model, pilots, and (optionally) received
+    vectors to detect with their outputs.  Tensors are device tensors as for
+    train() and detect()."""
+
+    model: Model
+    rx_pilot: object
+    sym_pilot: object
+    rx: object = None
+    modulation: object = "qpsk"
+    soft: object = None
+    hard: object = None
+    truth: object = None
+    errors: object = None
+    sigma2: Optional[float] = None
+
+
+class Batch:
+    """Detectors of different shapes trained in one launch and detected in one
+    launch (apsm_batch_* of the C ABI).  The workspace is a uint8 device tensor
+    owned by this object; every tensor named by the items is kept alive."""
+
+    def __init__(self, params: Params, items: Sequence[BatchItem], stream=None):
+        torch = _torch()
+        if not items:
+            raise ValueError("a batch needs at least one item")
+        self.items = list(items)
+        arr = (_CBatchItem * len(items))()
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        for c, it in zip(arr, self.items):
+            m = it.model
+            P = it.rx_pilot.shape[0]
+            _check(it.rx_pilot, torch.float32, (P, m.M2), "rx_pilot")
+            _check(it.sym_pilot, torch.float32, (P, m.K, 2), "sym_pilot")
+            S = 0 if it.rx is None else it.rx.shape[0]
+            if it.rx is not None:
+                _check(it.rx, torch.float32, (S, m.M2), "rx")
+            if it.soft is not None:
+                _check(it.soft, torch.float32, (S, m.K, 2), "soft")
+            if it.hard is not None:
+                _check(it.hard, torch.uint8, (S, m.K), "hard")
+            if it.truth is not None:
+                _check(it.truth, torch.uint8, (S, m.K), "truth")
+            if it.errors is not None:
+                _check(it.errors, torch.int64, (m.K,), "errors")
+            sig = float(it.sigma2 if it.sigma2 is not None else params.sigma2)
+            m.sigma2 = sig
+            c.model = m._c()
+            c.sigma2 = sig
+            c.P = P
+            c.rx_pilot = ptr(it.rx_pilot)
+            c.sym_pilot = ptr(it.sym_pilot)
+            c.S = S
+            c.modulation = _MODS[it.modulation]
+            c.rx = ptr(it.rx)
+            c.soft = ptr(it.soft)
+            c.hard = ptr(it.hard)
+            c.truth = ptr(it.truth)
+            c.err_count = ptr(it.errors)
+        p, keep = params._c()
+        h = ctypes.c_void_p()
+        rc = library().apsm_batch_create(ctypes.byref(p), arr, len(items), ctypes.byref(h))
+        del keep
+        if rc:
+            raise APSMError(rc, "apsm_batch_create")
+        self._h = h
+        nbytes = library().apsm_batch_workspace_bytes(h)
+        dev = self.items[0].rx_pilot.device
+        self.workspace = torch.zeros(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        rc = library().apsm_batch_bind(h, self._ws_ptr, nbytes, _stream_handle(stream))
+        if rc:
+            raise APSMError(rc, "apsm_batch_bind")
+
+    def tune(self, stream=None) -> "Batch":
+        rc = library().apsm_batch_tune(self._h, _stream_handle(stream))
+        if rc:
+            raise APSMError(rc, "apsm_batch_tune")
+        return self
+
+    def train(self, stream=None) -> "Batch":
+        rc = library().apsm_batch_train(self._h, _stream_handle(stream))
+        if rc:
+            raise APSMError(rc, "apsm_batch_train")
+        return self
+
+    def detect(self, stream=None) -> "Batch":
+        rc = library().apsm_batch_detect(self._h, _stream_handle(stream))
+        if rc:
+            raise APSMError(rc, "apsm_batch_detect")
+        return self
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().apsm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass

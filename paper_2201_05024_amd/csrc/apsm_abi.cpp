@@ -8,8 +8,10 @@
 #include "apsm_internal.h"
 
 namespace {
-
 thread_local std::string g_last_hip_error;
+}  // namespace
+
+namespace apsm {
 
 int hip_status(hipError_t e) {
   if (e == hipSuccess) return APSM_OK;
@@ -29,7 +31,74 @@ int check_model(const apsm_model_t* m) {
   return APSM_OK;
 }
 
-}  // namespace
+int check_params(const apsm_params_t* p) {
+  if (!p) return APSM_ERR_INVALID_ARG;
+  if (!finite_pos(p->sigma2) || !std::isfinite(p->eps) || p->eps < 0.0f) return APSM_ERR_INVALID_ARG;
+  if (!(p->mu > 0.0f && p->mu < 2.0f)) return APSM_ERR_INVALID_ARG;
+  if (!std::isfinite(p->w_lin) || !std::isfinite(p->w_gauss) || p->w_lin < 0.0f ||
+      p->w_gauss < 0.0f || (p->w_lin == 0.0f && p->w_gauss == 0.0f))
+    return APSM_ERR_INVALID_ARG;
+  if (p->reserved != 0 || p->window < 1) return APSM_ERR_INVALID_ARG;
+  if (p->window > APSM_MAX_WINDOW) return APSM_ERR_UNSUPPORTED;
+  if (p->dict_cap < p->window) return APSM_ERR_INVALID_ARG;
+  if (p->pos_weights) {
+    for (int i = 0; i < p->window; ++i)
+      if (!finite_pos(p->pos_weights[i])) return APSM_ERR_INVALID_ARG;
+  }
+  return APSM_OK;
+}
+
+void fill_common(const apsm_params_t* p, TrainCommon& cm) {
+  cm.W = p->window;
+  cm.eps = p->eps;
+  cm.mu = p->mu;
+  cm.wl = p->w_lin;
+  cm.wg = p->w_gauss;
+  for (int i = 0; i < APSM_MAX_WINDOW; ++i) cm.omega[i] = 1.0f;
+  if (p->pos_weights)
+    for (int i = 0; i < p->window; ++i) cm.omega[i] = p->pos_weights[i];
+}
+
+int check_detect_args(int M2, int K, float sigma2, int S, const float* rx, float* soft, uint8_t* hard,
+                      int modulation, const uint8_t* truth, int64_t* err_count) {
+  (void)M2;
+  (void)K;
+  if (!finite_pos(sigma2)) return APSM_ERR_INVALID_ARG;
+  if (S < 0) return APSM_ERR_SHAPE;
+  if (modulation != APSM_MOD_NONE && modulation != APSM_MOD_QPSK && modulation != APSM_MOD_QAM16)
+    return APSM_ERR_INVALID_ARG;
+  if (S == 0) return APSM_OK;                  // nothing to read or write; pointers may be NULL
+  if ((hard || truth || err_count) && modulation == APSM_MOD_NONE) return APSM_ERR_INVALID_ARG;
+  if ((truth == nullptr) != (err_count == nullptr)) return APSM_ERR_INVALID_ARG;
+  if (!soft && !hard && !err_count) return APSM_ERR_INVALID_ARG;
+  if (!rx) return APSM_ERR_INVALID_ARG;
+  return APSM_OK;
+}
+
+DetectArgs detect_args(const apsm_model_t* model, float sigma2, int S, const float* rx, float* soft,
+                       uint8_t* hard, int modulation, const uint8_t* truth, int64_t* err_count) {
+  DetectArgs a{};
+  a.dict = model->dict;
+  a.alpha = model->alpha;
+  a.w = model->w;
+  a.state = model->state;
+  a.packed = static_cast<const unsigned char*>(model->packed);
+  a.rx = rx;
+  a.soft = soft;
+  a.hard = hard;
+  a.truth = truth;
+  a.err = reinterpret_cast<unsigned long long*>(err_count);
+  a.cap = model->dict_cap;
+  a.M2 = model->M2;
+  a.M = model->M2 / 2;
+  a.K = model->K;
+  a.S = S;
+  a.modulation = modulation;
+  a.c2 = kLog2e / (2.0f * sigma2);
+  return a;
+}
+
+}  // namespace apsm
 
 extern "C" {
 
@@ -48,24 +117,10 @@ const char* apsm_strerror(int code) {
 
 const char* apsm_last_hip_error(void) { return g_last_hip_error.c_str(); }
 
-namespace {
+}  // extern "C"
 
-int check_params(const apsm_params_t* p) {
-  if (!p) return APSM_ERR_INVALID_ARG;
-  if (!finite_pos(p->sigma2) || !std::isfinite(p->eps) || p->eps < 0.0f) return APSM_ERR_INVALID_ARG;
-  if (!(p->mu > 0.0f && p->mu < 2.0f)) return APSM_ERR_INVALID_ARG;
-  if (!std::isfinite(p->w_lin) || !std::isfinite(p->w_gauss) || p->w_lin < 0.0f ||
-      p->w_gauss < 0.0f || (p->w_lin == 0.0f && p->w_gauss == 0.0f))
-    return APSM_ERR_INVALID_ARG;
-  if (p->reserved != 0 || p->window < 1) return APSM_ERR_INVALID_ARG;
-  if (p->window > APSM_MAX_WINDOW) return APSM_ERR_UNSUPPORTED;
-  if (p->dict_cap < p->window) return APSM_ERR_INVALID_ARG;
-  if (p->pos_weights) {
-    for (int i = 0; i < p->window; ++i)
-      if (!finite_pos(p->pos_weights[i])) return APSM_ERR_INVALID_ARG;
-  }
-  return APSM_OK;
-}
+namespace {
+using namespace apsm;
 
 // Shared by apsm_train and apsm_train_batched: every check happens before the
 // first launch.
@@ -82,22 +137,14 @@ int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const f
   }
 
   apsm::TrainArgs a{};
+  fill_common(p, a.cm);
   a.rx = rx_pilot;
   a.sym = sym_pilot;
   a.P = P;
   a.M2 = M2;
-  a.M = M2 / 2;
   a.K = K;
-  a.W = p->window;
   a.cap = p->dict_cap;
   a.c2 = apsm::kLog2e / (2.0f * p->sigma2);
-  a.eps = p->eps;
-  a.mu = p->mu;
-  a.wl = p->w_lin;
-  a.wg = p->w_gauss;
-  for (int i = 0; i < APSM_MAX_WINDOW; ++i) a.omega[i] = 1.0f;
-  if (p->pos_weights)
-    for (int i = 0; i < p->window; ++i) a.omega[i] = p->pos_weights[i];
 
   for (int b0 = 0; b0 < n_inst; b0 += apsm::kMaxTrainBatch) {
     const int nb = n_inst - b0 < apsm::kMaxTrainBatch ? n_inst - b0 : apsm::kMaxTrainBatch;
@@ -123,6 +170,8 @@ int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const f
 }
 
 }  // namespace
+
+extern "C" {
 
 int apsm_train(const apsm_params_t* p, int M2, int K, int P, const float* rx_pilot,
                const float* sym_pilot, const apsm_model_t* model, void* stream) {
@@ -153,35 +202,11 @@ int apsm_detect(const apsm_model_t* model, float sigma2, int S, const float* rx,
                 uint8_t* hard, int modulation, const uint8_t* truth, int64_t* err_count,
                 void* stream) {
   if (int rc = check_model(model)) return rc;
-  if (!finite_pos(sigma2)) return APSM_ERR_INVALID_ARG;
-  if (S < 0) return APSM_ERR_SHAPE;
-  if (modulation != APSM_MOD_NONE && modulation != APSM_MOD_QPSK && modulation != APSM_MOD_QAM16)
-    return APSM_ERR_INVALID_ARG;
-  if (S == 0) return APSM_OK;                  // nothing to read or write; pointers may be NULL
-  if ((hard || truth || err_count) && modulation == APSM_MOD_NONE) return APSM_ERR_INVALID_ARG;
-  if ((truth == nullptr) != (err_count == nullptr)) return APSM_ERR_INVALID_ARG;
-  if (!soft && !hard && !err_count) return APSM_ERR_INVALID_ARG;
-  if (!rx) return APSM_ERR_INVALID_ARG;
-
-  apsm::DetectArgs a{};
-  a.dict = model->dict;
-  a.alpha = model->alpha;
-  a.w = model->w;
-  a.state = model->state;
-  a.packed = static_cast<const unsigned char*>(model->packed);
-  a.rx = rx;
-  a.soft = soft;
-  a.hard = hard;
-  a.truth = truth;
-  a.err = reinterpret_cast<unsigned long long*>(err_count);
-  a.cap = model->dict_cap;
-  a.M2 = model->M2;
-  a.M = model->M2 / 2;
-  a.K = model->K;
-  a.S = S;
-  a.modulation = modulation;
-  a.c2 = apsm::kLog2e / (2.0f * sigma2);
-  return hip_status(apsm::launch_detect(a, (hipStream_t)stream));
+  if (int rc = check_detect_args(model->M2, model->K, sigma2, S, rx, soft, hard, modulation, truth, err_count))
+    return rc;
+  if (S == 0) return APSM_OK;
+  const DetectArgs a = detect_args(model, sigma2, S, rx, soft, hard, modulation, truth, err_count);
+  return hip_status(launch_detect(a, (hipStream_t)stream));
 }
 
 int apsm_get_status(const apsm_model_t* model, int32_t* host_state) {

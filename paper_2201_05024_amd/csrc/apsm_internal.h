@@ -16,22 +16,41 @@ constexpr float kLog2e = 1.4426950408889634f;
 // per-instance pointers fit the kernel-argument block.
 constexpr int kMaxTrainBatch = 32;
 
-// Everything the training kernel needs, by value (kernel arguments; no device
-// allocation, and a captured graph keeps a copy).  Workgroup b trains
-// instance b: pilots at rx + b * P * M2 and sym + b * P * K * 2, model
-// arrays dict[b], alpha[b], w[b], state[b].
-struct TrainArgs {
-  const float* rx;        // [n][P][M2] pilot vectors, r1 layout
-  const float* sym;       // [n][P][K][2]
-  float* dict[kMaxTrainBatch];   // [cap][M2] each
-  float* alpha[kMaxTrainBatch];  // [cap][K]
-  float* w[kMaxTrainBatch];      // [K][M2]
-  int32_t* state[kMaxTrainBatch];// [4]
-  int n_inst;
-  int P, M2, M, K, W, cap;
-  float c2;               // log2e / (2 sigma^2)
+// Parameters shared by every detector of a training launch.
+struct TrainCommon {
+  int W;                  // window size
   float eps, mu, wl, wg;
   float omega[APSM_MAX_WINDOW];   // position weights, omega[0] for j = n
+};
+
+// One detector's training job as the kernel body sees it.
+struct TrainJob {
+  const float* rx;        // [P][M2] pilot vectors, r1 layout
+  const float* sym;       // [P][K][2]
+  float* dict;            // [cap][M2]
+  float* alpha;           // [cap][K]
+  float* w;               // [K][M2]
+  int32_t* state;         // [4]
+  int P, M2, K, cap;
+  float c2;               // log2e / (2 sigma^2)
+  int variant;            // kernel specialisation (train_variant), table launches only
+};
+
+// Training launch of n_inst detectors of one shape, all by value (kernel
+// arguments; no device allocation, and a captured graph keeps a copy).
+// Workgroup b trains detector b: pilots at rx + b * P * M2 and
+// sym + b * P * K * 2, model arrays dict[b], alpha[b], w[b], state[b].
+struct TrainArgs {
+  TrainCommon cm;
+  const float* rx;        // [n][P][M2]
+  const float* sym;       // [n][P][K][2]
+  float* dict[kMaxTrainBatch];
+  float* alpha[kMaxTrainBatch];
+  float* w[kMaxTrainBatch];
+  int32_t* state[kMaxTrainBatch];
+  int n_inst;
+  int P, M2, K, cap;
+  float c2;
 };
 
 struct DetectArgs {
@@ -50,13 +69,74 @@ struct DetectArgs {
   float c2;               // log2e / (2 sigma^2)
 };
 
+// One detection job of a batched launch (same field names as DetectArgs).
+struct DetJob {
+  const unsigned char* packed;  // packed model (split-FP16 path)
+  const float* w;         // [K][M2]
+  const int32_t* state;   // [4]
+  const float* rx;        // [S][M2]
+  float* soft;            // [S][K][2] or null
+  uint8_t* hard;          // [S][K] or null
+  const uint8_t* truth;   // [S][K] or null
+  unsigned long long* err;// [K] or null
+  int cap, M2, K, S;
+  int modulation;
+  float c2;
+  int variant;            // detect_batch_variant
+  int pad;
+};
+
 // Launchers: return a hipError_t from the launch.
 hipError_t launch_train(const TrainArgs& a, hipStream_t stream);
+// Heterogeneous training: workgroup b runs jobs[b] (device table of n jobs,
+// each with its variant set by train_variant) with lds_bytes of dynamic LDS
+// (the largest train_lds_bytes of the jobs).
+int train_variant(int M2, int K, int cap);
+size_t train_lds_bytes(int W, int M2, int K);
+hipError_t launch_train_table(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
+                              hipStream_t stream);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t stream);
 // Packed model for the split-FP16 detection path: bytes (0 when the shape
 // uses the FP32 path) and the packing launch (no-op for such shapes).
 size_t packed_model_bytes(int M2, int K, int cap);
 hipError_t launch_pack_model(const float* dict, const float* alpha, const int32_t* state, int cap,
                              int M2, int K, void* packed, hipStream_t stream);
+
+// One model to pack in a batched packing launch (shapes of the split-FP16
+// path only); variant = detect_batch_variant(M2, K).
+struct PackJob {
+  const float* dict;
+  const float* alpha;
+  const int32_t* state;
+  unsigned char* packed;
+  int cap, M2, K, variant;
+};
+// Packs jobs[0..n) (device table), max_cap the largest capacity among them.
+hipError_t launch_pack_model_batch(const PackJob* jobs, int n, int max_cap, hipStream_t stream);
+
+// Batched detection.  Jobs whose shape has detect_batch_variant >= 0 run in
+// one launch over a global sequence of work items, item i being tile
+// items[i].y (64 received vectors) of job items[i].x, ordered by the host
+// (most expensive tiles first).  With ctr == null, workgroup b runs item b
+// (grid = n_items); otherwise `grid` persistent workgroups claim items in
+// order through ctr[0], ctr[1] counts finished workgroups and the last one
+// resets both to zero (they must be zero before the first launch and stay
+// zero between launches).
+int detect_batch_variant(int M2, int K);
+int detect_tiles(int S);
+int detect_batch_grid();
+hipError_t launch_detect_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr,
+                               int grid, hipStream_t stream);
+
+// Host helpers of the ABI layer (apsm_abi.cpp), shared with the batch layer.
+int hip_status(hipError_t e);              // APSM_OK or APSM_ERR_HIP (text kept)
+bool finite_pos(float x);
+int check_model(const apsm_model_t* m);
+int check_params(const apsm_params_t* p);
+void fill_common(const apsm_params_t* p, TrainCommon& cm);
+int check_detect_args(int M2, int K, float sigma2, int S, const float* rx, float* soft, uint8_t* hard,
+                      int modulation, const uint8_t* truth, int64_t* err_count);
+DetectArgs detect_args(const apsm_model_t* model, float sigma2, int S, const float* rx, float* soft,
+                       uint8_t* hard, int modulation, const uint8_t* truth, int64_t* err_count);
 
 }  // namespace apsm

@@ -1,0 +1,304 @@
+// Batches of detectors with different shapes: host planning of the job
+// tables, the device workspace image, the launch forms of batched detection
+// and their tuning.
+//
+// Planning: every item becomes one training job (one workgroup, its kernel
+// specialisation picked by train_variant), ordered by estimated cost so the
+// longest trainings start first.  Items whose shape the split-FP16 path
+// covers (2M <= 64, K <= 8) become packing jobs and detection jobs; their
+// 64-vector tiles form one global work-item list, ordered by the cost of a
+// tile (dictionary size times per-entry work), most expensive first.  Other
+// items are detected by their own apsm_detect launch after the batched one.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "apsm_internal.h"
+
+struct apsm_batch {
+  std::vector<apsm_batch_item_t> items;
+  apsm::TrainCommon cm{};
+  std::vector<apsm::TrainJob> tjobs;
+  size_t train_lds = 0;
+  std::vector<apsm::PackJob> pjobs;
+  int pack_max_cap = 0;
+  std::vector<apsm::DetJob> djobs;
+  std::vector<int2> ditems;
+  std::vector<int> plain;            // items detected with their own launch
+  size_t off_t = 0, off_p = 0, off_d = 0, off_i = 0, off_c = 0, bytes = 0;
+  unsigned char* ws = nullptr;       // bound workspace (device)
+  bool persistent = true;
+  int grid = 0;
+  uint64_t signature = 0;
+};
+
+namespace {
+
+using namespace apsm;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int check_item(const apsm_batch_item_t& it, int window) {
+  if (int rc = check_model(&it.model)) return rc;
+  if (it.model.dict_cap < window) return APSM_ERR_INVALID_ARG;
+  if (it.P < 1) return APSM_ERR_SHAPE;
+  if ((long long)it.P * 2 > (long long)INT32_MAX / 2) return APSM_ERR_UNSUPPORTED;
+  if (!it.rx_pilot || !it.sym_pilot) return APSM_ERR_INVALID_ARG;
+  return check_detect_args(it.model.M2, it.model.K, it.sigma2, it.S, it.rx, it.soft, it.hard, it.modulation,
+                           it.truth, it.err_count);
+}
+
+uint64_t fnv(uint64_t h, int64_t v) {
+  for (int b = 0; b < 8; ++b) {
+    h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Shape mix of a batch: the tuned launch form is reused for equal mixes.
+uint64_t signature_of(const std::vector<apsm_batch_item_t>& items) {
+  uint64_t h = 1469598103934665603ull;
+  for (const auto& it : items) {
+    h = fnv(h, it.model.M2);
+    h = fnv(h, it.model.K);
+    h = fnv(h, it.model.dict_cap);
+    h = fnv(h, it.P);
+    h = fnv(h, it.S);
+  }
+  return h;
+}
+
+std::mutex g_tune_mutex;
+std::map<uint64_t, bool> g_tuned;   // signature -> persistent form chosen
+
+bool tuned_choice(uint64_t sig, bool* persistent) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  auto f = g_tuned.find(sig);
+  if (f == g_tuned.end()) return false;
+  *persistent = f->second;
+  return true;
+}
+
+void plan(apsm_batch& b, const apsm_params_t* p) {
+  const int n = (int)b.items.size();
+  fill_common(p, b.cm);
+
+  // training: longest first (steps x entries swept per step x width)
+  std::vector<double> tcost(n);
+  for (int i = 0; i < n; ++i) {
+    const auto& it = b.items[i];
+    const double T = 2.0 * it.P;
+    const double D = std::min<double>(T, it.model.dict_cap);
+    tcost[i] = T * (D * (it.model.M2 + it.model.K) + 64.0 * p->window);
+  }
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tcost[a] > tcost[c]; });
+  for (int i : order) {
+    const auto& it = b.items[i];
+    TrainJob j{};
+    j.rx = it.rx_pilot;
+    j.sym = it.sym_pilot;
+    j.dict = it.model.dict;
+    j.alpha = it.model.alpha;
+    j.w = it.model.w;
+    j.state = it.model.state;
+    j.P = it.P;
+    j.M2 = it.model.M2;
+    j.K = it.model.K;
+    j.cap = it.model.dict_cap;
+    j.c2 = kLog2e / (2.0f * it.sigma2);
+    j.variant = train_variant(j.M2, j.K, j.cap);
+    b.tjobs.push_back(j);
+    b.train_lds = std::max(b.train_lds, train_lds_bytes(p->window, j.M2, j.K));
+  }
+
+  // packing and detection
+  std::vector<int> det;
+  for (int i = 0; i < n; ++i) {
+    const auto& it = b.items[i];
+    const int v = detect_batch_variant(it.model.M2, it.model.K);
+    if (v < 0) {
+      if (it.S > 0) b.plain.push_back(i);
+      continue;
+    }
+    PackJob pj{};
+    pj.dict = it.model.dict;
+    pj.alpha = it.model.alpha;
+    pj.state = it.model.state;
+    pj.packed = static_cast<unsigned char*>(it.model.packed);
+    pj.cap = it.model.dict_cap;
+    pj.M2 = it.model.M2;
+    pj.K = it.model.K;
+    pj.variant = v;
+    b.pjobs.push_back(pj);
+    b.pack_max_cap = std::max(b.pack_max_cap, pj.cap);
+    if (it.S > 0) det.push_back(i);
+  }
+  std::vector<double> dcost(n, 0.0);
+  for (int i : det) {
+    const auto& it = b.items[i];
+    const double D = std::min<double>(2.0 * it.P, it.model.dict_cap);
+    dcost[i] = (std::ceil(D / 64.0) + 0.25) * (it.model.K + 6 + it.model.M2 / 16.0);
+  }
+  std::stable_sort(det.begin(), det.end(), [&](int a, int c) { return dcost[a] > dcost[c]; });
+  for (int i : det) {
+    const auto& it = b.items[i];
+    DetJob d{};
+    d.packed = static_cast<const unsigned char*>(it.model.packed);
+    d.w = it.model.w;
+    d.state = it.model.state;
+    d.rx = it.rx;
+    d.soft = it.soft;
+    d.hard = it.hard;
+    d.truth = it.truth;
+    d.err = reinterpret_cast<unsigned long long*>(it.err_count);
+    d.cap = it.model.dict_cap;
+    d.M2 = it.model.M2;
+    d.K = it.model.K;
+    d.S = it.S;
+    d.modulation = it.modulation;
+    d.c2 = kLog2e / (2.0f * it.sigma2);
+    d.variant = detect_batch_variant(d.M2, d.K);
+    const int job = (int)b.djobs.size();
+    b.djobs.push_back(d);
+    const int tiles = detect_tiles(it.S);
+    for (int t = 0; t < tiles; ++t) b.ditems.push_back(make_int2(job, t));
+  }
+
+  b.off_t = 0;
+  b.off_p = align256(b.off_t + b.tjobs.size() * sizeof(TrainJob));
+  b.off_d = align256(b.off_p + b.pjobs.size() * sizeof(PackJob));
+  b.off_i = align256(b.off_d + b.djobs.size() * sizeof(DetJob));
+  b.off_c = align256(b.off_i + b.ditems.size() * sizeof(int2));
+  b.bytes = b.off_c + 256;
+  b.signature = signature_of(b.items);
+  bool pers = true;
+  if (tuned_choice(b.signature, &pers)) b.persistent = pers;
+}
+
+template <class T>
+const T* at(const apsm_batch* b, size_t off) {
+  return reinterpret_cast<const T*>(b->ws + off);
+}
+
+int run_detect(const apsm_batch* b, bool persistent, hipStream_t stream) {
+  if (!b->ditems.empty()) {
+    unsigned int* ctr = persistent ? reinterpret_cast<unsigned int*>(b->ws + b->off_c) : nullptr;
+    hipError_t e = launch_detect_batch(at<DetJob>(b, b->off_d), at<int2>(b, b->off_i), (int)b->ditems.size(), ctr,
+                                       b->grid, stream);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  for (int i : b->plain) {
+    const auto& it = b->items[i];
+    const DetectArgs a = detect_args(&it.model, it.sigma2, it.S, it.rx, it.soft, it.hard, it.modulation,
+                                     it.truth, it.err_count);
+    hipError_t e = launch_detect(a, stream);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return APSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* items, int n, apsm_batch_t** out) {
+  if (!params || !items || !out || n < 1) return APSM_ERR_INVALID_ARG;
+  *out = nullptr;
+  apsm_params_t pc = *params;
+  pc.sigma2 = 1.0f;                // per item
+  pc.dict_cap = pc.window;         // per item
+  if (int rc = check_params(&pc)) return rc;
+  for (int i = 0; i < n; ++i)
+    if (int rc = check_item(items[i], params->window)) return rc;
+  apsm_batch* b = new (std::nothrow) apsm_batch();
+  if (!b) return APSM_ERR_INVALID_ARG;
+  b->items.assign(items, items + n);
+  plan(*b, &pc);
+  if (b->ditems.size() > (size_t)INT32_MAX) {
+    delete b;
+    return APSM_ERR_UNSUPPORTED;
+  }
+  *out = b;
+  return APSM_OK;
+}
+
+size_t apsm_batch_workspace_bytes(const apsm_batch_t* b) { return b ? b->bytes : 0; }
+
+int apsm_batch_bind(apsm_batch_t* b, void* workspace, size_t bytes, void* stream) {
+  if (!b || !workspace) return APSM_ERR_INVALID_ARG;
+  if (bytes < b->bytes || (reinterpret_cast<uintptr_t>(workspace) & 255)) return APSM_ERR_INVALID_ARG;
+  std::vector<unsigned char> img(b->bytes, 0);
+  if (!b->tjobs.empty()) std::memcpy(img.data() + b->off_t, b->tjobs.data(), b->tjobs.size() * sizeof(TrainJob));
+  if (!b->pjobs.empty()) std::memcpy(img.data() + b->off_p, b->pjobs.data(), b->pjobs.size() * sizeof(PackJob));
+  if (!b->djobs.empty()) std::memcpy(img.data() + b->off_d, b->djobs.data(), b->djobs.size() * sizeof(DetJob));
+  if (!b->ditems.empty()) std::memcpy(img.data() + b->off_i, b->ditems.data(), b->ditems.size() * sizeof(int2));
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(workspace, img.data(), b->bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_status(e);
+  b->ws = static_cast<unsigned char*>(workspace);
+  b->grid = detect_batch_grid();
+  return APSM_OK;
+}
+
+int apsm_batch_train(const apsm_batch_t* b, void* stream) {
+  if (!b || !b->ws) return APSM_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_train_table(at<TrainJob>(b, b->off_t), (int)b->tjobs.size(), b->cm, b->train_lds, s);
+  if (e == hipSuccess) e = launch_pack_model_batch(at<PackJob>(b, b->off_p), (int)b->pjobs.size(), b->pack_max_cap, s);
+  return hip_status(e);
+}
+
+int apsm_batch_detect(const apsm_batch_t* b, void* stream) {
+  if (!b || !b->ws) return APSM_ERR_INVALID_ARG;
+  return run_detect(b, b->persistent, (hipStream_t)stream);
+}
+
+int apsm_batch_tune(apsm_batch_t* b, void* stream) {
+  if (!b || !b->ws) return APSM_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (b->ditems.empty()) return APSM_OK;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError());
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return hip_status(hipGetLastError());
+  }
+  float best[2] = {0.0f, 0.0f};
+  int rc = APSM_OK;
+  for (int form = 0; form < 2 && rc == APSM_OK; ++form) {
+    const bool pers = form == 1;
+    rc = run_detect(b, pers, s);                           // warm-up
+    float tmin = 0.0f;
+    for (int rep = 0; rep < 3 && rc == APSM_OK; ++rep) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess) rc = run_detect(b, pers, s);
+      if (rc == APSM_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+      if (rc == APSM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (rc == APSM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) rc = hip_status(e);
+      if (rep == 0 || ms < tmin) tmin = ms;
+    }
+    best[form] = tmin;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != APSM_OK) return rc;
+  b->persistent = best[1] <= best[0];
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tuned[b->signature] = b->persistent;
+  return APSM_OK;
+}
+
+void apsm_batch_destroy(apsm_batch_t* b) { delete b; }
+
+}  // extern "C"

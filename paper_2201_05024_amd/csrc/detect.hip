@@ -14,6 +14,10 @@ hipError_t launch_pack_model(const float* dict, const float* alpha, const int32_
   return f16::launch_pack(dict, alpha, state, cap, M2, K, static_cast<unsigned char*>(packed), stream);
 }
 
+hipError_t launch_pack_model_batch(const PackJob* jobs, int n, int max_cap, hipStream_t stream) {
+  return f16::launch_pack_batch(jobs, n, max_cap, stream);
+}
+
 hipError_t launch_detect(const DetectArgs& a, hipStream_t stream) {
   if (f16::supported(a.M2, a.K)) {
     const int M2P = f16::pad16(a.M2);

@@ -1,0 +1,101 @@
+// Batched detection (Sec. III-B evaluation of many frozen filters at once):
+// one launch over the tiles of many detectors of different shapes (user
+// count K, input dimension 2M, dictionary size).  Each tile runs the
+// split-FP16 tile body specialised for its detector's (2M, K), chosen by a
+// switch on the job's variant, so a single function holds every
+// specialisation and the LDS of the largest.
+//
+// Work items are (job, tile) pairs in an order the host fixes (most
+// expensive tiles first).  In the persistent form a grid sized to the chip
+// claims them one at a time from an atomic counter, so expensive tiles start
+// first and the short ones fill the tail; in the plain form workgroup b runs
+// item b and the hardware dispatcher hands out workgroups in that same order.
+#include "detect_f16.h"
+
+namespace apsm {
+namespace f16 {
+namespace {
+
+// variant = 8 * (M2P / 16 == 1 ? 0 : M2P == 32 ? 1 : 2) + K - 1
+#define APSM_F16_VARIANTS_M(X, base, M2P)                                           \
+  X(base + 0, M2P, 1) X(base + 1, M2P, 2) X(base + 2, M2P, 3) X(base + 3, M2P, 4)   \
+  X(base + 4, M2P, 5) X(base + 5, M2P, 6) X(base + 6, M2P, 7) X(base + 7, M2P, 8)
+#define APSM_F16_VARIANTS(X) \
+  APSM_F16_VARIANTS_M(X, 0, 16) APSM_F16_VARIANTS_M(X, 8, 32) APSM_F16_VARIANTS_M(X, 16, 64)
+
+constexpr int kBatchLds = tile_lds_bytes<64, 8>();   // the largest specialisation
+static_assert(tile_lds_bytes<64, 7>() <= kBatchLds && tile_lds_bytes<32, 8>() <= kBatchLds, "LDS bound");
+
+__device__ __forceinline__ void run_item(const DetJob& d, int tile, unsigned char* lds, unsigned int* werr) {
+  switch (d.variant) {
+#define APSM_F16_CASE(id, M2P, K) \
+  case id: detect_f16_tile<M2P, K>(d, d.packed, tile, lds, werr); break;
+    APSM_F16_VARIANTS(APSM_F16_CASE)
+#undef APSM_F16_CASE
+    default: break;
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void detect_batch_kernel(const DetJob* jobs, const int2* items,
+                                                                   int n_items, unsigned int* ctr) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kBatchLds];
+  __shared__ unsigned int werr[8];
+  __shared__ int s_item;
+  if (ctr == nullptr) {
+    const int2 it = items[blockIdx.x];
+    run_item(jobs[it.x], it.y, lds, werr);
+    return;
+  }
+  for (;;) {
+    // Every thread has read s_item of the previous item before that item's
+    // first barrier, so thread 0 may overwrite it here.
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(ctr, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= n_items) break;
+    const int2 it = items[item];
+    run_item(jobs[it.x], it.y, lds, werr);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    // This workgroup's last claim precedes its count; the workgroup that
+    // counts last therefore sees every claim done and restores the zeros.
+    const unsigned int done = atomicAdd(ctr + 1, 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(ctr, 0u);
+      atomicExch(ctr + 1, 0u);
+    }
+  }
+}
+
+}  // namespace
+}  // namespace f16
+
+int detect_batch_variant(int M2, int K) {
+  if (!f16::supported(M2, K)) return -1;
+  const int M2P = f16::pad16(M2);
+  return 8 * (M2P == 16 ? 0 : M2P == 32 ? 1 : 2) + K - 1;
+}
+
+int detect_tiles(int S) { return (S + f16::kWaves * 16 - 1) / (f16::kWaves * 16); }
+
+// Two workgroups per CU: the specialisations use up to 256 VGPRs (two waves
+// per SIMD) and two copies of the largest LDS footprint fit a CU.
+int detect_batch_grid() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 512;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 512;
+  return 2 * cus;
+}
+
+hipError_t launch_detect_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr, int grid,
+                               hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  const int blocks = ctr ? grid : n_items;
+  hipLaunchKernelGGL(f16::detect_batch_kernel, dim3(blocks), dim3(f16::kThreads), 0, stream, jobs, items,
+                     n_items, ctr);
+  return hipGetLastError();
+}
+
+}  // namespace apsm

@@ -80,6 +80,7 @@ __device__ __forceinline__ int scale_exp(float maxabs) {
   return 13 - ex;
 }
 
+hipError_t launch_pack_batch(const PackJob* jobs, int n, int max_cap, hipStream_t stream);
 hipError_t launch_pack(const float* dict, const float* alpha, const int32_t* state, int cap, int M2,
                        int K, unsigned char* packed, hipStream_t stream);
 hipError_t launch_detect_f16_m16(const DetectArgs& a, const unsigned char* packed, hipStream_t stream);
@@ -125,18 +126,26 @@ struct Prefetch {
   }
 };
 
+// LDS bytes of one tile: two dictionary stages and the linear coefficients.
 template <int M2P, int K>
-__global__ __launch_bounds__(kThreads, 2) void detect_f16_kernel(DetectArgs a, const unsigned char* packed) {
+constexpr int tile_lds_bytes() { return 2 * Geo<M2P, K>::STAGE_BYTES + K * M2P * 4; }
+
+// Detection of one tile of kWaves * 16 received vectors (vectors tile * 64 ..
+// tile * 64 + 63) by the whole workgroup.  A is DetectArgs or DetJob (the same
+// field names); lds holds tile_lds_bytes<M2P, K>() bytes (16-byte aligned),
+// werr 8 counters.  A workgroup may run tiles back to back on the same LDS
+// when a barrier separates them.
+template <int M2P, int K, class A>
+__device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char* packed, int tile,
+                                                unsigned char* lds, unsigned int* werr) {
   using G = Geo<M2P, K>;
   constexpr int NSTEP = G::NSTEP, NB = G::NB, KE = G::KE, K4 = G::K4, CSTR = G::CSTR;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * G::STAGE_BYTES + K * M2P * 4];
-  __shared__ unsigned int werr[8];
   float* wl = reinterpret_cast<float*>(lds + 2 * G::STAGE_BYTES);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int j = lane & 31, h = lane >> 5;
-  const int M2 = a.M2, M = a.M;
+  const int M2 = a.M2, M = a.M2 / 2;
   const int cap64 = cap64_of(a.cap);
   int D = a.state[0];
   D = D < 0 ? 0 : (D > a.cap ? a.cap : D);
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(kThreads, 2) void detect_f16_kernel(DetectArgs a, c
   // ---- A fragments: row j of this wave's tile is sample s0 + j/2, part j%2
   // (r1 for part 0, r2 = [Im; -Re] for part 1); this lane holds components
   // 16 b + 8 h + v of it.
-  const int s0 = (blockIdx.x * kWaves + wave) * 16;
+  const int s0 = (tile * kWaves + wave) * 16;
   const int my_smp = s0 + (j >> 1), my_part = j & 1;
   const bool my_valid = my_smp < a.S;
   const float* x = a.rx + (size_t)(my_valid ? my_smp : 0) * M2;
@@ -312,6 +321,13 @@ __global__ __launch_bounds__(kThreads, 2) void detect_f16_kernel(DetectArgs a, c
     __syncthreads();
     if (tid < K && werr[tid]) atomicAdd(a.err + tid, (unsigned long long)werr[tid]);
   }
+}
+
+template <int M2P, int K>
+__global__ __launch_bounds__(kThreads, 2) void detect_f16_kernel(DetectArgs a, const unsigned char* packed) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[tile_lds_bytes<M2P, K>()];
+  __shared__ unsigned int werr[8];
+  detect_f16_tile<M2P, K>(a, packed, blockIdx.x, lds, werr);
 }
 
 }  // namespace f16

@@ -8,15 +8,15 @@ namespace apsm {
 namespace f16 {
 namespace {
 
-// One workgroup: header[0] = exponent placing max |d| in [2^12, 2^13).
-__global__ __launch_bounds__(1024) void dict_scale_kernel(const float* dict, const int32_t* state, int cap,
-                                                          int M2, int* header) {
+// One workgroup of 1024 threads: header[0] = exponent placing max |d| in
+// [2^12, 2^13), header[1] = entries in use.
+__device__ __forceinline__ void dict_scale_body(const float* dict, const int32_t* state, int cap, int M2,
+                                                int* header, float* red) {
   int D = state[0];
   D = D < 0 ? 0 : (D > cap ? cap : D);
   float m = 0.0f;
   const size_t n = (size_t)D * M2;
   for (size_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(dict[i]));
-  __shared__ float red[1024];
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
@@ -29,12 +29,18 @@ __global__ __launch_bounds__(1024) void dict_scale_kernel(const float* dict, con
   }
 }
 
+__global__ __launch_bounds__(1024) void dict_scale_kernel(const float* dict, const int32_t* state, int cap,
+                                                          int M2, int* header) {
+  __shared__ float red[1024];
+  dict_scale_body(dict, state, cap, M2, header, red);
+}
+
+// Row i of the packed model (one thread per row; rows up to cap64).
 template <int M2P, int K>
-__global__ __launch_bounds__(256) void pack_kernel(const float* dict, const float* alpha, const int32_t* state,
-                                                   int cap, int M2, unsigned char* out) {
+__device__ __forceinline__ void pack_row(const float* dict, const float* alpha, const int32_t* state, int cap,
+                                         int M2, unsigned char* out, int i) {
   using G = Geo<M2P, K>;
   const int cap64 = cap64_of(cap);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cap64) return;
   int D = state[0];
   D = D < 0 ? 0 : (D > cap ? cap : D);
@@ -56,6 +62,36 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* dict, const floa
   for (int k = 0; k < G::K4; ++k) co[k] = (valid && k < K) ? alpha[(size_t)i * K + k] : 0.0f;
   co[G::K4] = n;
   co[G::K4 + 1] = co[G::K4 + 2] = co[G::K4 + 3] = 0.0f;
+}
+
+template <int M2P, int K>
+__global__ __launch_bounds__(256) void pack_kernel(const float* dict, const float* alpha, const int32_t* state,
+                                                   int cap, int M2, unsigned char* out) {
+  pack_row<M2P, K>(dict, alpha, state, cap, M2, out, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched packing: workgroup (x, y) packs rows 256 x .. 256 x + 255 of job y.
+__global__ __launch_bounds__(1024) void dict_scale_batch_kernel(const PackJob* jobs) {
+  __shared__ float red[1024];
+  const PackJob j = jobs[blockIdx.x];
+  dict_scale_body(j.dict, j.state, j.cap, j.M2, reinterpret_cast<int*>(j.packed), red);
+}
+
+__global__ __launch_bounds__(256) void pack_batch_kernel(const PackJob* jobs) {
+  const PackJob j = jobs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  switch (j.variant) {
+#define APSM_PACK_CASE(M2P, K, id) \
+  case id: pack_row<M2P, K>(j.dict, j.alpha, j.state, j.cap, j.M2, j.packed, i); break;
+    APSM_PACK_CASE(16, 1, 0) APSM_PACK_CASE(16, 2, 1) APSM_PACK_CASE(16, 3, 2) APSM_PACK_CASE(16, 4, 3)
+    APSM_PACK_CASE(16, 5, 4) APSM_PACK_CASE(16, 6, 5) APSM_PACK_CASE(16, 7, 6) APSM_PACK_CASE(16, 8, 7)
+    APSM_PACK_CASE(32, 1, 8) APSM_PACK_CASE(32, 2, 9) APSM_PACK_CASE(32, 3, 10) APSM_PACK_CASE(32, 4, 11)
+    APSM_PACK_CASE(32, 5, 12) APSM_PACK_CASE(32, 6, 13) APSM_PACK_CASE(32, 7, 14) APSM_PACK_CASE(32, 8, 15)
+    APSM_PACK_CASE(64, 1, 16) APSM_PACK_CASE(64, 2, 17) APSM_PACK_CASE(64, 3, 18) APSM_PACK_CASE(64, 4, 19)
+    APSM_PACK_CASE(64, 5, 20) APSM_PACK_CASE(64, 6, 21) APSM_PACK_CASE(64, 7, 22) APSM_PACK_CASE(64, 8, 23)
+#undef APSM_PACK_CASE
+    default: break;
+  }
 }
 
 template <int M2P, int K>
@@ -86,6 +122,16 @@ hipError_t pack_m(const float* dict, const float* alpha, const int32_t* state, i
 }
 
 }  // namespace
+
+// The scale pass must finish before rows are packed (they read header[0]):
+// two launches in stream order.
+hipError_t launch_pack_batch(const PackJob* jobs, int n, int max_cap, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dict_scale_batch_kernel, dim3(n), dim3(1024), 0, stream, jobs);
+  const int blocks = (cap64_of(max_cap) + 255) / 256;
+  hipLaunchKernelGGL(pack_batch_kernel, dim3(blocks, n), dim3(256), 0, stream, jobs);
+  return hipGetLastError();
+}
 
 hipError_t launch_pack(const float* dict, const float* alpha, const int32_t* state, int cap, int M2, int K,
                        unsigned char* packed, hipStream_t stream) {

@@ -143,23 +143,25 @@ __device__ __forceinline__ float sweep(const float* x, int xs, const float* y, i
   return (a0 + a1) + (a2 + a3);
 }
 
+// Training of one detector by one workgroup of kThreads threads.  lds_raw
+// holds lds_floats(W, KP, M2P) floats.
 template <int M2P, int KP, int SLOTS>
-__global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
-  extern __shared__ float lds_raw[];
+__device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon& cm, float* lds_raw,
+                                           int* block_flags_p) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int W = a.W, R = W + 1, cap = a.cap, K = a.K, M2 = a.M2, M = a.M;
-  const int T = 2 * a.P;
+  const int W = cm.W, R = W + 1, cap = j.cap, K = j.K, M2 = j.M2, M = j.M2 / 2;
+  const int T = 2 * j.P;
   const int EVS = W > 1 ? W - 1 : 1;
   const int KM = K * M2;
   Lds s = carve(lds_raw, W, KP, M2P);
-  const int inst = blockIdx.x;
-  const float* rx = a.rx + (size_t)inst * a.P * M2;
-  const float* sym = a.sym + (size_t)inst * a.P * K * 2;
-  float* const dict = a.dict[inst];
-  float* const alpha = a.alpha[inst];
-  float* const wout = a.w[inst];
-  int32_t* const state = a.state[inst];
+  const float* rx = j.rx;
+  const float* sym = j.sym;
+  float* const dict = j.dict;
+  float* const alpha = j.alpha;
+  float* const wout = j.w;
+  int32_t* const state = j.state;
+  int& block_flags = *block_flags_p;
 
   for (int i = tid; i < W * KP; i += kThreads) {
     s.e[i] = 0.0f;
@@ -167,11 +169,11 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     s.c[i + W * KP] = 0.0f;
     s.bwin[i] = 0.0f;
   }
-  if (tid < W) s.omega[tid] = a.omega[tid];
+  if (tid < W) s.omega[tid] = cm.omega[tid];
   if (tid == 0) {
     float acc = 0.0f;
     s.qden[0] = 0.0f;
-    for (int p = 0; p < W; ++p) { acc += a.omega[p]; s.qden[p + 1] = acc; }
+    for (int p = 0; p < W; ++p) { acc += cm.omega[p]; s.qden[p + 1] = acc; }
   }
 
   // Linear coefficients: entry e = k * M2 + m lives in a register of thread
@@ -204,7 +206,6 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     // Model buffers hold the dictionary; start from an empty one.
     for (size_t i = tid; i < (size_t)cap * K; i += kThreads) alpha[i] = 0.0f;
   }
-  __shared__ int block_flags;
   if (tid == 0) block_flags = 0;
   int flags = 0;
 
@@ -277,12 +278,12 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
 #pragma unroll
           for (int m = 0; m < M2P; ++m) d4[m & 3] = fmaf(rn[m], dreg[u][m], d4[m & 3]);
           const float dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-          const float kg = __builtin_amdgcn_exp2f(a.c2 * (2.0f * dot - nn - dnorm[u]));
+          const float kg = __builtin_amdgcn_exp2f(j.c2 * (2.0f * dot - nn - dnorm[u]));
 #pragma unroll
           for (int k = 0; k < KP; ++k) part[k] = fmaf(areg[u][k], kg, part[k]);
           if (back < L) {
             const int ir = ring_sub(nr, back, R);
-            const float g = fmaf(a.wl, dot, a.wg * kg);
+            const float g = fmaf(cm.wl, dot, cm.wg * kg);
             s.gram[nr * R + ir] = g;
             s.gram[(nr + R) * R + ir] = g;
             s.gram[ir * R + nr] = g;
@@ -310,13 +311,13 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
           dot = fmaf(rrow[m], dv, dot);
           dn = fmaf(dv, dv, dn);
         }
-        const float kg = __builtin_amdgcn_exp2f(a.c2 * (2.0f * dot - nn - dn));
+        const float kg = __builtin_amdgcn_exp2f(j.c2 * (2.0f * dot - nn - dn));
 #pragma unroll
         for (int k = 0; k < KP; ++k)
           if (k < K) part[k] = fmaf(arow[k], kg, part[k]);
         if (back < L) {
           const int ir = ring_sub(nr, back, R);
-          const float g = fmaf(a.wl, dot, a.wg * kg);
+          const float g = fmaf(cm.wl, dot, cm.wg * kg);
           s.gram[nr * R + ir] = g;
           s.gram[(nr + R) * R + ir] = g;
           s.gram[ir * R + nr] = g;
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
     __syncthreads();
 
     // ------------------------------------------------------------ phase C
-    const float qscale = a.mu / s.qden[L];
+    const float qscale = cm.mu / s.qden[L];
     for (int t = tid; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
       const int jw = ring_sub(nw, p, W);
@@ -352,8 +353,8 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
         s.e[jw * KP + k] = e;
         const float x = e - s.bwin[jw * KP + k];
         if (!isfinite(x)) flags |= 1;
-        const float kjj = fmaf(a.wl, s.nrm[jw], a.wg);
-        const float beta = kjj > 0.0f ? -soft_threshold(x, a.eps) / kjj : 0.0f;
+        const float kjj = fmaf(cm.wl, s.nrm[jw], cm.wg);
+        const float beta = kjj > 0.0f ? -soft_threshold(x, cm.eps) / kjj : 0.0f;
         c = qscale * s.omega[p] * beta;
       }
       s.c[jw * KP + k] = c;
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
         w0 = fmaf(cw[-q * KP], rw[-q * M2P], w0);
       }
       if (has_e) s.e[ring_sub(nw, ep, W) * KP + ek] += e0 + e1;
-      if (has_w) wreg[0] = fmaf(a.wl, w0 + w1, wreg[0]);
+      if (has_w) wreg[0] = fmaf(cm.wl, w0 + w1, wreg[0]);
     }
     for (int t = tid + kThreads; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
           if (back < L) {
             const float* cj = cbase - back * KP;
 #pragma unroll
-            for (int k = 0; k < KP; ++k) areg[u][k] = fmaf(cj[k], a.wg, areg[u][k]);
+            for (int k = 0; k < KP; ++k) areg[u][k] = fmaf(cj[k], cm.wg, areg[u][k]);
           }
         }
       }
@@ -422,14 +423,14 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
         if ((slot & (kThreads - 1)) != tid) continue;
         const float* cj = cbase - q * KP;
         float* arow = alpha + (size_t)slot * K;
-        for (int k = 0; k < K; ++k) arow[k] = fmaf(cj[k], a.wg, arow[k]);
+        for (int k = 0; k < K; ++k) arow[k] = fmaf(cj[k], cm.wg, arow[k]);
       }
     }
 #pragma unroll
     for (int u = 1; u < WPT; ++u) {
       if (wk[u] >= KP) continue;
       const float acc = sweep(cbase + wk[u], KP, s.rwin + (nr + R) * M2P + wm[u], M2P, L);
-      wreg[u] = fmaf(a.wl, acc, wreg[u]);
+      wreg[u] = fmaf(cm.wl, acc, wreg[u]);
     }
     // Phase A of the next step touches only ring rows that no window member
     // of this step uses (the Gram and vector rings have W + 1 rows; the
@@ -475,9 +476,88 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   }
 }
 
+// Detectors of one shape, described in the kernel arguments.
+template <int M2P, int KP, int SLOTS>
+__global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
+  extern __shared__ float lds_raw[];
+  __shared__ int block_flags;
+  const int b = blockIdx.x;
+  TrainJob j;
+  j.rx = a.rx + (size_t)b * a.P * a.M2;
+  j.sym = a.sym + (size_t)b * a.P * a.K * 2;
+  j.dict = a.dict[b];
+  j.alpha = a.alpha[b];
+  j.w = a.w[b];
+  j.state = a.state[b];
+  j.P = a.P;
+  j.M2 = a.M2;
+  j.K = a.K;
+  j.cap = a.cap;
+  j.c2 = a.c2;
+  j.variant = 0;
+  train_body<M2P, KP, SLOTS>(j, a.cm, lds_raw, &block_flags);
+}
+
+// Register-resident dictionary slots per thread for a capacity: SLOTS * M2P
+// dictionary floats stay in registers when that is at most 128; larger
+// dictionaries live in the model buffers (SLOTS = 0).
+__host__ __device__ constexpr int slots_for(int M2P, int cap) {
+  const int need = (cap + kThreads - 1) / kThreads;
+  const int s = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
+  return (s > 0 && s * M2P <= 128) ? s : 0;
+}
+
+__host__ __device__ constexpr int kp_for(int K) { return K <= 4 ? 4 : K <= 8 ? 8 : 16; }
+__host__ __device__ constexpr int m2p_for(int M2) { return M2 <= 16 ? 16 : M2 <= 32 ? 32 : M2 <= 64 ? 64 : 128; }
+
+// Every specialisation (M2P, KP, SLOTS) with its variant number.
+#define APSM_TRAIN_VARIANTS_M(X, base, M2P, KP)                                    \
+  X(base + 0, M2P, KP, 0) X(base + 1, M2P, KP, 1) X(base + 2, M2P, KP, 2)          \
+  X(base + 3, M2P, KP, 4) X(base + 4, M2P, KP, 8)
+#define APSM_TRAIN_VARIANTS(X)                                                      \
+  APSM_TRAIN_VARIANTS_M(X, 0, 16, 4) APSM_TRAIN_VARIANTS_M(X, 5, 16, 8)            \
+  APSM_TRAIN_VARIANTS_M(X, 10, 16, 16) APSM_TRAIN_VARIANTS_M(X, 15, 32, 4)         \
+  APSM_TRAIN_VARIANTS_M(X, 20, 32, 8) APSM_TRAIN_VARIANTS_M(X, 25, 32, 16)         \
+  APSM_TRAIN_VARIANTS_M(X, 30, 64, 4) APSM_TRAIN_VARIANTS_M(X, 35, 64, 8)          \
+  APSM_TRAIN_VARIANTS_M(X, 40, 64, 16) APSM_TRAIN_VARIANTS_M(X, 45, 128, 4)        \
+  APSM_TRAIN_VARIANTS_M(X, 50, 128, 8) APSM_TRAIN_VARIANTS_M(X, 55, 128, 16)
+
+__host__ __device__ constexpr int variant_of(int M2P, int KP, int SLOTS) {
+  const int mi = M2P == 16 ? 0 : M2P == 32 ? 1 : M2P == 64 ? 2 : 3;
+  const int ki = KP == 4 ? 0 : KP == 8 ? 1 : 2;
+  const int si = SLOTS == 0 ? 0 : SLOTS == 1 ? 1 : SLOTS == 2 ? 2 : SLOTS == 4 ? 3 : 4;
+  return (mi * 3 + ki) * 5 + si;
+}
+
+// The table kernel holds the register-resident specialisations only where
+// they fit the register file on their own (no spill space needed); other
+// jobs take the model-buffer path (SLOTS = 0).  One function holding the
+// heavier ones as well would spill for all of them.
+__host__ __device__ constexpr bool in_table(int M2P, int KP, int SLOTS) {
+  return SLOTS == 0 || (SLOTS * (M2P + KP) <= 128 && !(M2P == 64 && KP == 16));
+}
+
+// Detectors of any shapes, one job per workgroup from a device table; each
+// job runs the specialisation its variant names.
+__global__ __launch_bounds__(kThreads) void train_table_kernel(const TrainJob* jobs, TrainCommon cm) {
+  extern __shared__ float lds_raw[];
+  __shared__ int block_flags;
+  const TrainJob j = jobs[blockIdx.x];
+  switch (j.variant) {
+#define APSM_TRAIN_CASE(id, M2P, KP, SLOTS)                                         \
+  case id:                                                                          \
+    if constexpr (SLOTS * M2P <= 128 && in_table(M2P, KP, SLOTS)) train_body<M2P, KP, SLOTS>(j, cm, lds_raw, &block_flags); \
+    break;
+    APSM_TRAIN_VARIANTS(APSM_TRAIN_CASE)
+#undef APSM_TRAIN_CASE
+    default:
+      break;
+  }
+}
+
 template <int M2P, int KP, int SLOTS>
 hipError_t launch_one(const TrainArgs& a, hipStream_t stream) {
-  const size_t bytes = lds_floats(a.W, KP, M2P) * sizeof(float);
+  const size_t bytes = lds_floats(a.cm.W, KP, M2P) * sizeof(float);
   auto kern = train_kernel<M2P, KP, SLOTS>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -488,17 +568,13 @@ hipError_t launch_one(const TrainArgs& a, hipStream_t stream) {
 
 template <int M2P, int KP>
 hipError_t pick_slots(const TrainArgs& a, hipStream_t stream) {
-  const int slots = (a.cap + kThreads - 1) / kThreads;
-  // Registers hold SLOTS * M2P dictionary floats per thread; keep that modest
-  // (larger dictionaries stay in the model buffers).
-  if constexpr (M2P <= 128)
-    if (slots <= 1) return launch_one<M2P, KP, 1>(a, stream);
-  if constexpr (2 * M2P <= 128)
-    if (slots <= 2) return launch_one<M2P, KP, 2>(a, stream);
-  if constexpr (4 * M2P <= 128)
-    if (slots <= 4) return launch_one<M2P, KP, 4>(a, stream);
-  if constexpr (8 * M2P <= 128)
-    if (slots <= 8) return launch_one<M2P, KP, 8>(a, stream);
+  switch (slots_for(M2P, a.cap)) {
+    case 1: return launch_one<M2P, KP, 1>(a, stream);
+    case 2: if constexpr (2 * M2P <= 128) return launch_one<M2P, KP, 2>(a, stream); break;
+    case 4: if constexpr (4 * M2P <= 128) return launch_one<M2P, KP, 4>(a, stream); break;
+    case 8: if constexpr (8 * M2P <= 128) return launch_one<M2P, KP, 8>(a, stream); break;
+    default: break;
+  }
   return launch_one<M2P, KP, 0>(a, stream);
 }
 
@@ -517,6 +593,26 @@ hipError_t launch_train(const TrainArgs& a, hipStream_t stream) {
   if (a.M2 <= 64) return pick_k<64>(a, stream);
   if (a.M2 <= 128) return pick_k<128>(a, stream);
   return hipErrorInvalidValue;
+}
+
+int train_variant(int M2, int K, int cap) {
+  const int M2P = m2p_for(M2), KP = kp_for(K);
+  const int slots = slots_for(M2P, cap);
+  return variant_of(M2P, KP, in_table(M2P, KP, slots) ? slots : 0);
+}
+
+size_t train_lds_bytes(int W, int M2, int K) {
+  return lds_floats(W, kp_for(K), m2p_for(M2)) * sizeof(float);
+}
+
+hipError_t launch_train_table(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
+                              hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(train_table_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(train_table_kernel, dim3(n), dim3(kThreads), lds_bytes, stream, jobs, cm);
+  return hipGetLastError();
 }
 
 }  // namespace apsm

@@ -170,3 +170,22 @@ def spec_slot(snr_db: float, seed: int = BASE_SEED + 2, S: int = 1 << 20,
 
 def spec_paper_shape(seed: int = BASE_SEED + 6) -> InstanceSpec:
     return InstanceSpec(K=6, M=16, P=685, S=3840, snr_db=20.0, modulation="qpsk", seed=seed)
+
+
+BATCH_INSTANCES = 256
+
+
+def spec_batch_mixed(i: int, seed: int = BASE_SEED + 3, S: int = 1 << 16):
+    """Instance i of the batched mixed-shape workload: K uniform in {2..8}
+    users, M in {8, 16, 32} antennas, dictionary size D uniform in [64, 2048]
+    with P = D pilots (so the capacity binds after half the training steps),
+    QPSK or 16-QAM by a fair coin, SNR uniform in [5, 20] dB, unit user powers.
+    Returns (spec, D)."""
+    rng = np.random.default_rng([seed, i])
+    K = int(rng.integers(2, 9))
+    M = int(rng.choice([8, 16, 32]))
+    D = int(rng.integers(64, 2049))
+    mod = "qam16" if rng.random() < 0.5 else "qpsk"
+    snr = float(rng.uniform(5.0, 20.0))
+    spec = InstanceSpec(K=K, M=M, P=D, S=S, snr_db=snr, modulation=mod, seed=seed * 1000 + i)
+    return spec, D

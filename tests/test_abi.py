@@ -126,3 +126,69 @@ def test_packed_bytes():
     assert L.apsm_model_packed_bytes(128, 16, 1000) == 0      # detected without a packed form
     assert L.apsm_model_packed_bytes(33, 6, 10) == 0          # invalid shape
     assert L.apsm_model_pack(None, None) == 1
+
+
+def _item(**kw):
+    it = A._CBatchItem()
+    it.model = kw.pop("model", _model())
+    base = dict(sigma2=0.5, P=64, rx_pilot=1, sym_pilot=1, S=100, modulation=2, rx=1, soft=1, hard=1,
+                truth=1, err_count=1)
+    base.update(kw)
+    for k, v in base.items():
+        setattr(it, k, v)
+    return it
+
+
+@needs_lib
+def test_batch_create_plans_on_the_host():
+    """apsm_batch_create validates and plans without touching the device; the
+    workspace holds the job tables, one work item per 64 received vectors of
+    the detectors on the split-FP16 path, and the claim counters."""
+    L = A.library()
+    items = (A._CBatchItem * 3)(_item(), _item(model=_model(M2=16, K=2, cap=100), S=65),
+                                _item(model=_model(M2=128, K=16, cap=100, packed=None), S=1000))
+    h = ctypes.c_void_p()
+    assert L.apsm_batch_create(ctypes.byref(_params()), items, 3, ctypes.byref(h)) == 0
+    nbytes = L.apsm_batch_workspace_bytes(h)
+    # 3 training jobs, 2 packing jobs, 2 detection jobs, 2 + 2 tiles, counters; each table 256-aligned
+    assert nbytes >= 256 * 5 and nbytes % 256 == 0
+    assert L.apsm_batch_train(h, None) == 1          # not bound to a workspace yet
+    assert L.apsm_batch_detect(h, None) == 1
+    assert L.apsm_batch_bind(h, None, nbytes, None) == 1
+    assert L.apsm_batch_bind(h, 256, nbytes - 1, None) == 1   # too small
+    assert L.apsm_batch_bind(h, 257, nbytes, None) == 1       # misaligned
+    L.apsm_batch_destroy(h)
+    L.apsm_batch_destroy(None)
+
+
+BAD_ITEMS = [
+    dict(sigma2=0.0), dict(P=0), dict(rx_pilot=None), dict(S=-1), dict(modulation=3),
+    dict(truth=None), dict(soft=None, hard=None, err_count=None, truth=None), dict(rx=None),
+    dict(model=_model(cap=8)),                           # capacity below the window
+    dict(model=_model(packed=None)),                     # packed form required for this shape
+    dict(modulation=0),                                  # decisions asked without a modulation
+]
+
+
+@needs_lib
+@pytest.mark.parametrize("kw", BAD_ITEMS)
+def test_batch_create_rejects_bad_items(kw):
+    L = A.library()
+    items = (A._CBatchItem * 2)(_item(), _item(**kw))
+    h = ctypes.c_void_p(1234)
+    assert L.apsm_batch_create(ctypes.byref(_params()), items, 2, ctypes.byref(h)) != 0
+    assert not h.value
+
+
+@needs_lib
+def test_batch_create_rejects_bad_arguments():
+    L = A.library()
+    items = (A._CBatchItem * 1)(_item())
+    h = ctypes.c_void_p()
+    assert L.apsm_batch_create(None, items, 1, ctypes.byref(h)) == 1
+    assert L.apsm_batch_create(ctypes.byref(_params()), None, 1, ctypes.byref(h)) == 1
+    assert L.apsm_batch_create(ctypes.byref(_params()), items, 0, ctypes.byref(h)) == 1
+    assert L.apsm_batch_create(ctypes.byref(_params(mu=3.0)), items, 1, ctypes.byref(h)) == 1
+    # sigma2 and dict_cap of the shared parameters are not used by batches
+    assert L.apsm_batch_create(ctypes.byref(_params(sigma2=0.0, dict_cap=0)), items, 1, ctypes.byref(h)) == 0
+    L.apsm_batch_destroy(h)
