@@ -244,6 +244,58 @@ int apsm_batch_detect(const apsm_batch_t* batch, void* stream);
 /* Release the host object (not the workspace).  NULL is allowed. */
 void apsm_batch_destroy(apsm_batch_t* batch);
 
+/* ---- differentiable unrolled training ---------------------------------
+ * A batch of n_inst detectors of one shape trained by `passes` unrolled
+ * iterations, each one full pass of the windowed projections (Sec. II-D
+ * eqn:apsm, eqn:beta) over the T = 2P real training samples: pass 1 is the
+ * training of apsm_train with an unbounded dictionary (dict_cap >= 2P), later
+ * passes project onto the same hyperslabs again, restarting the window; then
+ * the filters are evaluated on S validation symbols (Sec. III-B) and
+ *     L = mean over instances, users and symbols of |g_k - b_k|^2.
+ * The parameters theta (DEVICE float[3 + window]) are shared by the batch:
+ *     theta[0] = sigma   (Gaussian kernel exp(-||u-v||^2 / (2 sigma^2)), > 0)
+ *     theta[1] = eps     (hyperslab half-width, >= 0)
+ *     theta[2] = mu      (relaxation, f <- f + mu sum_j q_j beta_j kappa(r_j, .))
+ *     theta[3 + p] = omega[p] > 0, q_j = omega[n-j] / sum_{i in J_n} omega[n-i].
+ * theta lives in device memory and is not checked on the host.
+ * apsm_unrolled_backward gives dL/dtheta with a hand-written adjoint (reverse
+ * sweep over the steps); it re-runs the forward from checkpoints taken every
+ * ckpt_every passes, one segment at a time, so memory holds the checkpoints
+ * and one segment's record instead of every step.  The gradient does not
+ * depend on ckpt_every (bit for bit).  At |x| = eps the slab is closed and
+ * the threshold's derivative is taken as 0. */
+typedef struct apsm_unrolled {
+  int32_t n_inst;       /* detectors, >= 1                                      */
+  int32_t P;            /* pilots per detector (T = 2P), 1..2048                */
+  int32_t M2;           /* 2M, even, 2..APSM_MAX_M2                             */
+  int32_t K;            /* users, 1..APSM_MAX_K                                 */
+  int32_t S;            /* validation symbols per detector, >= 1               */
+  int32_t passes;       /* unrolled iterations, >= 1                            */
+  int32_t ckpt_every;   /* checkpoint interval in passes, >= 1                  */
+  int32_t window;       /* W, 1..APSM_MAX_WINDOW                                */
+  float w_lin, w_gauss; /* sum-space weights (as apsm_params_t)                 */
+} apsm_unrolled_t;
+
+/* Device workspace bytes for this shape (training Gram matrix and squared
+ * distances, checkpoints, one segment's record, adjoint state). */
+size_t apsm_unrolled_workspace_bytes(const apsm_unrolled_t* u);
+
+/* Forward: loss (DEVICE float[1]) = L.  Inputs, contiguous DEVICE arrays:
+ *  rx_pilot [n][P][M2], sym_pilot [n][P][K][2], rx_val [n][S][M2],
+ *  sym_val [n][S][K][2].  workspace: >= apsm_unrolled_workspace_bytes,
+ *  256-byte aligned; keeps what the backward call needs. */
+int apsm_unrolled_forward(const apsm_unrolled_t* u, const float* theta, const float* rx_pilot,
+                          const float* sym_pilot, const float* rx_val, const float* sym_val,
+                          void* workspace, size_t ws_bytes, float* loss, void* stream);
+
+/* Backward: grad (DEVICE float[3 + window]) = upstream * dL/dtheta, with
+ * upstream a DEVICE float (NULL for 1).  Same arguments as the forward call
+ * it follows (same theta and inputs, same workspace); may be repeated. */
+int apsm_unrolled_backward(const apsm_unrolled_t* u, const float* theta, const float* rx_pilot,
+                           const float* sym_pilot, const float* rx_val, const float* sym_val,
+                           void* workspace, size_t ws_bytes, const float* upstream, float* grad,
+                           void* stream);
+
 /* Synchronous copy of model->state into host_state[4]; waits for all work on
  * the device. */
 int apsm_get_status(const apsm_model_t* model, int32_t* host_state);

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 from typing import Optional, Sequence
 
 __all__ = ["Params", "Model", "train", "train_batched", "detect", "Batch", "BatchItem", "APSMError",
-           "library", "LIB_PATH", "MOD_NONE", "MOD_QPSK", "MOD_QAM16"]
+           "unrolled_loss", "APSMUnrolled", "library", "LIB_PATH", "MOD_NONE", "MOD_QPSK", "MOD_QAM16"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapsm.so")
 
@@ -51,6 +51,13 @@ class _CBatchItem(ctypes.Structure):
                 ("S", ctypes.c_int32), ("modulation", ctypes.c_int32), ("rx", ctypes.c_void_p),
                 ("soft", ctypes.c_void_p), ("hard", ctypes.c_void_p), ("truth", ctypes.c_void_p),
                 ("err_count", ctypes.c_void_p)]
+
+
+class _CUnrolled(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("P", ctypes.c_int32), ("M2", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("S", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("w_lin", ctypes.c_float), ("w_gauss", ctypes.c_float)]
 
 
 _lib = None
@@ -94,6 +101,14 @@ def library() -> ctypes.CDLL:
         L.apsm_batch_detect.restype = i32
         L.apsm_batch_destroy.argtypes = [vp]
         L.apsm_batch_destroy.restype = None
+        L.apsm_unrolled_workspace_bytes.argtypes = [ctypes.POINTER(_CUnrolled)]
+        L.apsm_unrolled_workspace_bytes.restype = ctypes.c_size_t
+        L.apsm_unrolled_forward.argtypes = [ctypes.POINTER(_CUnrolled), vp, vp, vp, vp, vp, vp,
+                                            ctypes.c_size_t, vp, vp]
+        L.apsm_unrolled_forward.restype = i32
+        L.apsm_unrolled_backward.argtypes = [ctypes.POINTER(_CUnrolled), vp, vp, vp, vp, vp, vp,
+                                             ctypes.c_size_t, vp, vp, vp]
+        L.apsm_unrolled_backward.restype = i32
         L.apsm_strerror.argtypes = [i32]
         L.apsm_strerror.restype = ctypes.c_char_p
         L.apsm_last_hip_error.argtypes = []
@@ -373,3 +388,71 @@ class Batch:
             self.close()
         except Exception:  # pragma: no cover - interpreter shutdown
             pass
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class APSMUnrolledFn(torch.autograd.Function):
+        """L(theta) of unrolled APSM training (apsm_unrolled_forward) with the
+        library's hand-written adjoint as its backward (apsm_unrolled_backward)."""
+
+        @staticmethod
+        def forward(ctx, theta, rx_pilot, sym_pilot, rx_val, sym_val, passes, ckpt_every, w_lin, w_gauss):
+            n, P, M2 = rx_pilot.shape
+            K = sym_pilot.shape[2]
+            S = rx_val.shape[1]
+            W = theta.shape[0] - 3
+            _check(theta, torch.float32, (3 + W,), "theta")
+            _check(rx_pilot, torch.float32, (n, P, M2), "rx_pilot")
+            _check(sym_pilot, torch.float32, (n, P, K, 2), "sym_pilot")
+            _check(rx_val, torch.float32, (n, S, M2), "rx_val")
+            _check(sym_val, torch.float32, (n, S, K, 2), "sym_val")
+            u = _CUnrolled(n, P, M2, K, S, int(passes), int(ckpt_every), W, float(w_lin), float(w_gauss))
+            nbytes = library().apsm_unrolled_workspace_bytes(ctypes.byref(u))
+            if nbytes == 0:
+                raise APSMError(1, "apsm_unrolled_workspace_bytes")
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=theta.device)
+            ws_ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+            loss = torch.empty(1, dtype=torch.float32, device=theta.device)
+            args = (theta.data_ptr(), rx_pilot.data_ptr(), sym_pilot.data_ptr(), rx_val.data_ptr(),
+                    sym_val.data_ptr(), ws_ptr, nbytes)
+            rc = library().apsm_unrolled_forward(ctypes.byref(u), *args, loss.data_ptr(), _stream_handle(None))
+            if rc:
+                raise APSMError(rc, "apsm_unrolled_forward")
+            ctx.keep = (u, args, ws, theta, rx_pilot, sym_pilot, rx_val, sym_val)
+            return loss.reshape(())
+
+        @staticmethod
+        def backward(ctx, g_loss):
+            u, args, ws, theta = ctx.keep[:4]
+            up = g_loss.reshape(1).to(torch.float32).contiguous()
+            grad = torch.empty_like(theta)
+            rc = library().apsm_unrolled_backward(ctypes.byref(u), *args, up.data_ptr(), grad.data_ptr(),
+                                                  _stream_handle(None))
+            if rc:
+                raise APSMError(rc, "apsm_unrolled_backward")
+            return grad, None, None, None, None, None, None, None, None
+
+    return APSMUnrolledFn
+
+
+_APSM_UNROLLED = None
+
+
+def APSMUnrolled():
+    """The torch.autograd.Function class (created on first use)."""
+    global _APSM_UNROLLED
+    if _APSM_UNROLLED is None:
+        _APSM_UNROLLED = _autograd_function()
+    return _APSM_UNROLLED
+
+
+def unrolled_loss(theta, rx_pilot, sym_pilot, rx_val, sym_val, passes: int, ckpt_every: int = 5,
+                  w_lin: float = 0.5, w_gauss: float = 0.5):
+    """Differentiable L(theta), theta = [sigma, eps, mu, omega_0..omega_{W-1}]
+    (float32 device tensor); inputs [n][P][M2], [n][P][K][2], [n][S][M2],
+    [n][S][K][2] float32 device tensors.  loss.backward() runs the library's
+    adjoint."""
+    return APSMUnrolled().apply(theta, rx_pilot, sym_pilot, rx_val, sym_val, passes, ckpt_every, w_lin,
+                                w_gauss)

@@ -128,6 +128,26 @@ int detect_batch_grid();
 hipError_t launch_detect_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr,
                                int grid, hipStream_t stream);
 
+// Unrolled training and its adjoint.  Instance b's part of the workspace
+// starts at ws + b * inst_bytes; the off_* are byte offsets inside it.
+struct UnrolledArgs {
+  const float* theta;       // [3 + W] sigma, eps, mu, omega[0..W-1]
+  const float* rx_pilot;    // [n][P][M2]
+  const float* sym_pilot;   // [n][P][K][2]
+  const float* rx_val;      // [n][S][M2]
+  const float* sym_val;     // [n][S][K][2]
+  void* ws;
+  size_t inst_bytes;
+  size_t off_G, off_D, off_ck, off_st, off_sc, off_tx, off_th, off_adj, off_fbar, off_lpart, off_spart, off_gpart;
+  int n, P, T, M2, M2P, K, KP, S, W, WP, passes, E;
+  float wl, wg;
+  float inv_count;          // 1 / (n * S * K)
+};
+size_t unrolled_pass_lds(const UnrolledArgs& a);
+size_t unrolled_reverse_lds(const UnrolledArgs& a);
+hipError_t launch_unrolled_forward(const UnrolledArgs& a, float* loss, hipStream_t stream);
+hipError_t launch_unrolled_backward(const UnrolledArgs& a, float* grad, const float* upstream, hipStream_t stream);
+
 // Host helpers of the ABI layer (apsm_abi.cpp), shared with the batch layer.
 int hip_status(hipError_t e);              // APSM_OK or APSM_ERR_HIP (text kept)
 bool finite_pos(float x);

@@ -192,3 +192,31 @@ def test_batch_create_rejects_bad_arguments():
     # sigma2 and dict_cap of the shared parameters are not used by batches
     assert L.apsm_batch_create(ctypes.byref(_params(sigma2=0.0, dict_cap=0)), items, 1, ctypes.byref(h)) == 0
     L.apsm_batch_destroy(h)
+
+
+def _unr(**kw):
+    base = dict(n_inst=2, P=16, M2=8, K=3, S=10, passes=4, ckpt_every=2, window=8, w_lin=0.5, w_gauss=0.5)
+    base.update(kw)
+    return A._CUnrolled(**base)
+
+
+@needs_lib
+def test_unrolled_workspace_and_validation():
+    L = A.library()
+    u = _unr()
+    nbytes = L.apsm_unrolled_workspace_bytes(ctypes.byref(u))
+    T = 32
+    assert nbytes >= 2 * (2 * T * T * 4) and nbytes % 256 == 0
+    # more passes per checkpoint segment -> a longer record
+    assert L.apsm_unrolled_workspace_bytes(ctypes.byref(_unr(ckpt_every=4))) > nbytes
+    for bad in (dict(n_inst=0), dict(P=0), dict(P=4096), dict(M2=7), dict(M2=256), dict(K=0), dict(K=17),
+                dict(S=0), dict(passes=0), dict(ckpt_every=0), dict(window=0), dict(window=65),
+                dict(w_lin=0.0, w_gauss=0.0), dict(w_lin=-1.0)):
+        assert L.apsm_unrolled_workspace_bytes(ctypes.byref(_unr(**bad))) == 0, bad
+    args = [1, 1, 1, 1, 1]
+    assert L.apsm_unrolled_forward(ctypes.byref(_unr(K=0)), *args, 256, nbytes, 1, None) == 1
+    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 256, nbytes - 1, 1, None) == 1   # too small
+    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 257, nbytes, 1, None) == 1       # misaligned
+    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 256, nbytes, None, None) == 1    # no loss
+    assert L.apsm_unrolled_forward(ctypes.byref(u), None, 1, 1, 1, 1, 256, nbytes, 1, None) == 1
+    assert L.apsm_unrolled_backward(ctypes.byref(u), *args, 256, nbytes, None, None, None) == 1
