@@ -20,7 +20,7 @@ hipError_t launch_pack_model_batch(const PackJob* jobs, int n, int max_cap, hipS
 
 hipError_t launch_detect(const DetectArgs& a, hipStream_t stream) {
   if (f16::supported(a.M2, a.K)) {
-    const int M2P = f16::pad16(a.M2);
+    const int M2P = f16::m2p_f16(a.M2);
     if (M2P == 16) return f16::launch_detect_f16_m16(a, a.packed, stream);
     if (M2P == 32) return f16::launch_detect_f16_m32(a, a.packed, stream);
     return f16::launch_detect_f16_m64(a, a.packed, stream);

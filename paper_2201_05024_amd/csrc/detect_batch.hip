@@ -26,7 +26,44 @@ namespace {
 constexpr int kBatchLds = tile_lds_bytes<64, 8>();   // the largest specialisation
 static_assert(tile_lds_bytes<64, 7>() <= kBatchLds && tile_lds_bytes<32, 8>() <= kBatchLds, "LDS bound");
 
-__device__ __forceinline__ void run_item(const DetJob& d, int tile, unsigned char* lds, unsigned int* werr) {
+// Values every lane holds alike, moved to scalar registers so that the
+// compiler treats the control flow that depends on them (the item loop, the
+// switch, the dictionary-chunk loop around the tile's barriers) as uniform,
+// as it is: barriers must sit in uniform control flow.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(uni(__float_as_int(v))); }
+template <class P>
+__device__ __forceinline__ P* uni(P* p) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned long long lo = (unsigned)uni((int)(unsigned)u), hi = (unsigned)uni((int)(unsigned)(u >> 32));
+  return reinterpret_cast<P*>(lo | (hi << 32));
+}
+
+__device__ __forceinline__ DetJob load_job(const DetJob* p) {
+  DetJob d;
+  d.packed = uni(p->packed);
+  d.w = uni(p->w);
+  d.state = uni(p->state);
+  d.rx = uni(p->rx);
+  d.soft = uni(p->soft);
+  d.hard = uni(p->hard);
+  d.truth = uni(p->truth);
+  d.err = uni(p->err);
+  d.cap = uni(p->cap);
+  d.M2 = uni(p->M2);
+  d.K = uni(p->K);
+  d.S = uni(p->S);
+  d.modulation = uni(p->modulation);
+  d.c2 = uni(p->c2);
+  d.variant = uni(p->variant);
+  d.pad = 0;
+  return d;
+}
+
+__device__ __forceinline__ void run_item(const DetJob* jobs, const int2* items, int item, unsigned char* lds,
+                                         unsigned int* werr) {
+  const int jx = uni(items[item].x), tile = uni(items[item].y);
+  const DetJob d = load_job(jobs + jx);
   switch (d.variant) {
 #define APSM_F16_CASE(id, M2P, K) \
   case id: detect_f16_tile<M2P, K>(d, d.packed, tile, lds, werr); break;
@@ -36,26 +73,27 @@ __device__ __forceinline__ void run_item(const DetJob& d, int tile, unsigned cha
   }
 }
 
+// Next item of the persistent form: thread 0 claims it, every thread reads it
+// between two barriers (so the next claim cannot overwrite it early).
+__device__ __forceinline__ int claim(unsigned int* ctr, int* s_item) {
+  if (threadIdx.x == 0) *s_item = (int)atomicAdd(ctr, 1u);
+  __syncthreads();
+  const int item = uni(*s_item);
+  __syncthreads();
+  return item;
+}
+
 __global__ __launch_bounds__(kThreads, 2) void detect_batch_kernel(const DetJob* jobs, const int2* items,
                                                                    int n_items, unsigned int* ctr) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kBatchLds];
   __shared__ unsigned int werr[8];
   __shared__ int s_item;
   if (ctr == nullptr) {
-    const int2 it = items[blockIdx.x];
-    run_item(jobs[it.x], it.y, lds, werr);
+    run_item(jobs, items, blockIdx.x, lds, werr);
     return;
   }
-  for (;;) {
-    // Every thread has read s_item of the previous item before that item's
-    // first barrier, so thread 0 may overwrite it here.
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(ctr, 1u);
-    __syncthreads();
-    const int item = s_item;
-    if (item >= n_items) break;
-    const int2 it = items[item];
-    run_item(jobs[it.x], it.y, lds, werr);
-  }
+  for (int item = claim(ctr, &s_item); item < n_items; item = claim(ctr, &s_item))
+    run_item(jobs, items, item, lds, werr);
   if (threadIdx.x == 0) {
     __threadfence();
     // This workgroup's last claim precedes its count; the workgroup that
@@ -73,7 +111,7 @@ __global__ __launch_bounds__(kThreads, 2) void detect_batch_kernel(const DetJob*
 
 int detect_batch_variant(int M2, int K) {
   if (!f16::supported(M2, K)) return -1;
-  const int M2P = f16::pad16(M2);
+  const int M2P = f16::m2p_f16(M2);
   return 8 * (M2P == 16 ? 0 : M2P == 32 ? 1 : 2) + K - 1;
 }
 

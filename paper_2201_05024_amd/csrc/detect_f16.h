@@ -55,14 +55,17 @@ struct Geo {
   static constexpr int STAGE_BYTES = A_BYTES + C_BYTES;
 };
 
-__host__ __device__ inline int pad16(int m2) { return (m2 + 15) / 16 * 16; }
+// Padded input width of the specialisation that handles 2M = m2: 16, 32 or
+// 64.  The packed layout, its size and the kernel dispatch all use this one
+// value (a 2M of 40 runs, and is packed, with the 64-wide layout).
+__host__ __device__ inline int m2p_f16(int m2) { return m2 <= 16 ? 16 : m2 <= 32 ? 32 : 64; }
 __host__ __device__ inline int cap64_of(int cap) { return (cap + kChunk - 1) / kChunk * kChunk; }
 
 inline bool supported(int M2, int K) { return M2 <= 64 && K <= 8; }
 
 // Bytes of the packed model for a supported shape.
 inline size_t packed_bytes(int M2, int K, int cap) {
-  const int M2P = pad16(M2), K4 = (K + 3) / 4 * 4;
+  const int M2P = m2p_f16(M2), K4 = (K + 3) / 4 * 4;
   return kHeader + (size_t)cap64_of(cap) * ((2 * M2P + 8) * 2 + (K4 + 4) * 4);
 }
 
@@ -147,9 +150,12 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
   const int j = lane & 31, h = lane >> 5;
   const int M2 = a.M2, M = a.M2 / 2;
   const int cap64 = cap64_of(a.cap);
-  int D = a.state[0];
+  // Entries in use and the dictionary exponent are the same for every lane;
+  // in scalar registers they keep the chunk loop (which holds barriers)
+  // uniform control flow.
+  int D = __builtin_amdgcn_readfirstlane(a.state[0]);
   D = D < 0 ? 0 : (D > a.cap ? a.cap : D);
-  const int e_d = reinterpret_cast<const int*>(packed)[0];
+  const int e_d = __builtin_amdgcn_readfirstlane(reinterpret_cast<const int*>(packed)[0]);
 
   for (int e = tid; e < K * M2P; e += kThreads) {
     const int k = e / M2P, m = e - k * M2P;

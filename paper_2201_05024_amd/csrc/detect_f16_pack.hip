@@ -136,7 +136,7 @@ hipError_t launch_pack_batch(const PackJob* jobs, int n, int max_cap, hipStream_
 hipError_t launch_pack(const float* dict, const float* alpha, const int32_t* state, int cap, int M2, int K,
                        unsigned char* packed, hipStream_t stream) {
   if (!supported(M2, K)) return hipSuccess;      // shapes detected without a packed model
-  const int M2P = pad16(M2);
+  const int M2P = m2p_f16(M2);
   if (M2P == 16) return pack_m<16>(dict, alpha, state, cap, M2, K, packed, stream);
   if (M2P == 32) return pack_m<32>(dict, alpha, state, cap, M2, K, packed, stream);
   return pack_m<64>(dict, alpha, state, cap, M2, K, packed, stream);

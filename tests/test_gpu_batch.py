@@ -77,9 +77,15 @@ def test_batch_mixed_shapes_parity():
     insts, caps, sig = make_mixed()
     params = A.Params(eps=0.05, mu=1.0, window=W)
     batch, items = build_batch(insts, caps, sig, params)
-    batch.train().detect()
+    print("[step] batch planned and bound", flush=True)
+    batch.train()
     torch.cuda.synchronize()
+    print("[step] batch trained", flush=True)
+    batch.detect()
+    torch.cuda.synchronize()
+    print("[step] batch detected", flush=True)
     for i, (inst, cap, s2, it) in enumerate(zip(insts, caps, sig, items)):
+        print(f"[step] item {i}: {MIXED[i]}", flush=True)
         mod = inst.spec.modulation
         p = A.Params(sigma2=s2, eps=0.05, mu=1.0, window=W, dict_cap=cap)
         f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, oracle_params(p))

@@ -99,6 +99,8 @@ E2E_CASES = {
     "odd_m": (dict(K=2, M=3, P=90, S=211, snr_db=12.0), dict(window=5, dict_cap=77)),
     "k16_m64": (dict(K=16, M=64, P=96, S=130, snr_db=20.0, modulation="qam16"), dict(window=16, dict_cap=128)),
     "model_buffer_path": (dict(K=6, M=32, P=300, S=200, snr_db=10.0), dict(window=32, dict_cap=520)),
+    "m40_cap40": (dict(K=4, M=20, P=50, S=300, snr_db=12.0), dict(window=8, dict_cap=40)),
+    "m48": (dict(K=3, M=24, P=60, S=200, snr_db=12.0, modulation="qam16"), dict(window=8, dict_cap=100)),
     "sigma_paper": (dict(K=6, M=16, P=160, S=300, snr_db=20.0), dict(window=20, dict_cap=320, sigma2=0.05)),
     "near_far_rapp": (dict(K=6, M=16, P=256, S=512, snr_db=10.0, near_far_db=(-6.0, 0.0), rapp=(2.0, 1.0)),
                       dict(window=32, dict_cap=256)),
@@ -259,3 +261,34 @@ def test_batched_training_equals_single():
         torch.cuda.synchronize()
         for name in ("dict", "alpha", "w", "state", "packed"):
             assert torch.equal(getattr(models[idx], name), getattr(single, name)), (idx, name)
+
+
+@pytest.mark.parametrize("M2,K,cap", [(2, 1, 7), (6, 3, 40), (16, 8, 64), (18, 2, 65), (32, 6, 100), (34, 4, 40),
+                                      (40, 2, 40), (48, 5, 129), (62, 8, 64), (64, 7, 200), (66, 3, 50),
+                                      (128, 16, 64)])
+def test_training_and_packing_stay_inside_the_model(M2, K, cap):
+    """Every byte the library writes lies inside the caller's buffers: each
+    model array is carved from a larger buffer whose tail holds a guard
+    pattern, which must be intact after training (and packing)."""
+    P = 40
+    rng = np.random.default_rng(M2 * 100 + K)
+    rx = cuda(rng.normal(size=(P, M2)).astype(np.float32) * 0.3)
+    sym = cuda(rng.choice([-0.7071, 0.7071], size=(P, K, 2)).astype(np.float32))
+    m = A.Model(M2, K, cap, DEV, 0.5)
+    guards = {}
+    for name in ("dict", "alpha", "w", "state", "packed"):
+        t = getattr(m, name)
+        if t is None:
+            continue
+        nbytes = t.numel() * t.element_size()
+        buf = torch.full((nbytes + 8192,), 0xA5, dtype=torch.uint8, device=DEV)
+        buf[:nbytes].zero_()
+        setattr(m, name, buf[:nbytes].view(t.dtype).view(t.shape))
+        guards[name] = buf
+    A.train(rx, sym, A.Params(window=4, dict_cap=cap), model=m)
+    A.detect(m, rx, modulation="qpsk")
+    torch.cuda.synchronize()
+    for name, buf in guards.items():
+        t = getattr(m, name)
+        nbytes = t.numel() * t.element_size()
+        assert bool((buf[nbytes:] == 0xA5).all()), (name, M2, K, cap)
