@@ -92,8 +92,11 @@ typedef struct apsm_params {
 
 /* A trained detector: the whole filter state (Sec. III-B: dictionary plus
  * coefficients).  HOST struct of DEVICE pointers, all caller-allocated.
- *  dict   [dict_cap][M2]  Gaussian dictionary ring; slot of sample n is n % dict_cap;
- *                         unused slots hold zeros.
+ *  dict   [M2][dict_cap]  Gaussian dictionary ring, component-major: component m of
+ *                         the entry in slot i is dict[m * dict_cap + i] (so that the
+ *                         training and packing kernels read it with coalesced
+ *                         loads); slot of sample n is n % dict_cap; unused slots
+ *                         hold zeros.
  *  alpha  [dict_cap][K]   Gaussian coefficients (wG * gamma_i of Sec. II-D); zero for
  *                         unused slots.
  *  w      [K][M2]         linear coefficients (wL * gamma^(L) of Sec. II-D).

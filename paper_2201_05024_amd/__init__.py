@@ -175,7 +175,7 @@ class Model:
         torch = _torch()
         dev = device if device is not None else torch.device("cuda")
         self.M2, self.K, self.dict_cap, self.sigma2 = int(M2), int(K), int(dict_cap), float(sigma2)
-        self.dict = torch.zeros((dict_cap, M2), dtype=torch.float32, device=dev)
+        self.dict = torch.zeros((M2, dict_cap), dtype=torch.float32, device=dev)   # component-major
         self.alpha = torch.zeros((dict_cap, K), dtype=torch.float32, device=dev)
         self.w = torch.zeros((K, M2), dtype=torch.float32, device=dev)
         self.state = torch.zeros(4, dtype=torch.int32, device=dev)

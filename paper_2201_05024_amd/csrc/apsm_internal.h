@@ -27,7 +27,7 @@ struct TrainCommon {
 struct TrainJob {
   const float* rx;        // [P][M2] pilot vectors, r1 layout
   const float* sym;       // [P][K][2]
-  float* dict;            // [cap][M2]
+  float* dict;            // [M2][cap] component-major
   float* alpha;           // [cap][K]
   float* w;               // [K][M2]
   int32_t* state;         // [4]
@@ -54,7 +54,7 @@ struct TrainArgs {
 };
 
 struct DetectArgs {
-  const float* dict;      // [cap][M2]
+  const float* dict;      // [M2][cap] component-major
   const float* alpha;     // [cap][K]
   const float* w;         // [K][M2]
   const int32_t* state;   // [4], state[0] = entries in use

@@ -15,8 +15,8 @@ __device__ __forceinline__ void dict_scale_body(const float* dict, const int32_t
   int D = state[0];
   D = D < 0 ? 0 : (D > cap ? cap : D);
   float m = 0.0f;
-  const size_t n = (size_t)D * M2;
-  for (size_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(dict[i]));
+  for (int c = 0; c < M2; ++c)                      // component c of entries 0..D-1
+    for (int i = threadIdx.x; i < D; i += blockDim.x) m = fmaxf(m, fabsf(dict[(size_t)c * cap + i]));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
@@ -50,7 +50,7 @@ __device__ __forceinline__ void pack_row(const float* dict, const float* alpha, 
   float n = 0.0f;
 #pragma unroll 4
   for (int m = 0; m < M2P; ++m) {
-    const float d = (valid && m < M2) ? dict[(size_t)i * M2 + m] : 0.0f;
+    const float d = (valid && m < M2) ? dict[(size_t)m * cap + i] : 0.0f;
     n = fmaf(d, d, n);
     _Float16 hi, lo;
     split_f16(d * sc, hi, lo);

@@ -72,13 +72,13 @@ __device__ __forceinline__ void stage_chunk(float* st, const DetectArgs& a, int 
   const int rr = t / TPR, qq = t % TPR;
   const int row = row0 + rr;
   const bool valid = row < D;
-  const float* src = a.dict + (size_t)(valid ? row : 0) * a.M2;
+  const float* src = a.dict + (valid ? row : 0);     // component m at src[m * cap]
   float* dst = st + rr * G::ASTR;
   float nrm = 0.0f;
 #pragma unroll
   for (int m0 = 0; m0 < M2P; m0 += TPR) {
     const int m = m0 + qq;
-    const float v = ((valid && m < a.M2) ? 1.0f : 0.0f) * src[m < a.M2 ? m : 0];
+    const float v = ((valid && m < a.M2) ? 1.0f : 0.0f) * src[(size_t)(m < a.M2 ? m : 0) * a.cap];
     nrm = fmaf(v, v, nrm);
     dst[(m & 1) * G::KHP + (m >> 1)] = 2.0f * a.c2 * v;
   }

@@ -37,32 +37,17 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-// Reduce-scatter of KP per-lane values over the 64 lanes of a wave: returns,
-// in every lane L, the wave sum of value number L >> (6 - log2 KP).  Costs
-// KP - 1 + 6 - log2(KP) lane exchanges instead of 6 KP for KP full sums.
-template <int KP>
-__device__ __forceinline__ float wave_reduce_scatter(const float (&in)[KP]) {
-  constexpr int LOG = KP == 1 ? 0 : KP == 2 ? 1 : KP == 4 ? 2 : KP == 8 ? 3 : 4;
-  float v[KP];
-#pragma unroll
-  for (int i = 0; i < KP; ++i) v[i] = in[i];
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int t = 0; t < LOG; ++t) {
-    const int half = KP >> (t + 1);
-    const int mask = 32 >> t;
-    const bool upper = (lane & mask) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const float send = upper ? v[i] : v[half + i];
-      const float keep = upper ? v[half + i] : v[i];
-      v[i] = keep + __shfl_xor(send, mask);
-    }
-  }
-  float r = v[0];
-#pragma unroll
-  for (int t = LOG; t < 6; ++t) r += __shfl_xor(r, 32 >> t);
-  return r;
+// Sum over the 64 lanes of a wave; the result is valid in lane 63.  Six
+// DPP steps (quad swaps, row mirrors, row broadcasts) that stay in the
+// VALU, with no LDS round trip.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
 }
 
 __device__ __forceinline__ float soft_threshold(float x, float eps) {
@@ -294,43 +279,66 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         }
       }
     } else {
-      for (int slot = tid; slot < cap && slot <= n; slot += kThreads) {
-        float* drow = dict + (size_t)slot * M2;
-        float* arow = alpha + (size_t)slot * K;
-        if (slot == sn) {
-          if (evicting) {
-            for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
-          }
-          for (int m = 0; m < M2; ++m) drow[m] = rrow[m];
-          for (int k = 0; k < K; ++k) arow[k] = 0.0f;
-        }
-        const int back = ring_sub(sn, slot, cap);
-        float dot = 0.0f, dn = 0.0f;
-        for (int m = 0; m < M2; ++m) {
-          const float dv = drow[m];
-          dot = fmaf(rrow[m], dv, dot);
-          dn = fmaf(dv, dv, dn);
-        }
-        const float kg = __builtin_amdgcn_exp2f(j.c2 * (2.0f * dot - nn - dn));
+      // Model-buffer path: SB of this thread's slots at a time, every
+      // component of each loaded before any is used, so that SB * M2P loads
+      // are in flight at once (the dictionary is component-major: lanes read
+      // consecutive slots, coalesced).
+      constexpr int SB = M2P >= 128 ? 1 : M2P >= 64 ? 2 : 4;
+      const int nslot = (n + 1 < cap ? n + 1 : cap);        // slots in use after the append
+      if (tid == (sn & (kThreads - 1))) {                   // append (and evict)
+        float* arow = alpha + (size_t)sn * K;
+        if (evicting)
+          for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
+        for (int m = 0; m < M2; ++m) dict[(size_t)m * cap + sn] = rrow[m];
+        for (int k = 0; k < K; ++k) arow[k] = 0.0f;
+      }
+      for (int base = tid; base < nslot; base += SB * kThreads) {
+        float dv[SB][M2P];
+        float av[SB][KP];
 #pragma unroll
-        for (int k = 0; k < KP; ++k)
-          if (k < K) part[k] = fmaf(arow[k], kg, part[k]);
-        if (back < L) {
-          const int ir = ring_sub(nr, back, R);
-          const float g = fmaf(cm.wl, dot, cm.wg * kg);
-          s.gram[nr * R + ir] = g;
-          s.gram[(nr + R) * R + ir] = g;
-          s.gram[ir * R + nr] = g;
-          s.gram[(ir + R) * R + nr] = g;
+        for (int b = 0; b < SB; ++b) {
+          const int slot = base + b * kThreads;
+          const bool ok = slot < nslot;
+          const float* dcol = dict + (ok ? slot : 0);
+#pragma unroll
+          for (int m = 0; m < M2P; ++m) dv[b][m] = (ok && m < M2) ? dcol[(size_t)m * cap] : 0.0f;
+          const float* arow = alpha + (size_t)(ok ? slot : 0) * K;
+#pragma unroll
+          for (int k = 0; k < KP; ++k) av[b][k] = (ok && k < K) ? arow[k] : 0.0f;
         }
-        const int mv = n - back - evlo;
-        if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          const int slot = base + b * kThreads;
+          if (slot >= nslot) continue;
+          float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f}, n4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int m = 0; m < M2P; ++m) {
+            d4[m & 3] = fmaf(rrow[m], dv[b][m], d4[m & 3]);
+            n4[m & 3] = fmaf(dv[b][m], dv[b][m], n4[m & 3]);
+          }
+          const float dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+          const float dn = (n4[0] + n4[1]) + (n4[2] + n4[3]);
+          const float kg = __builtin_amdgcn_exp2f(j.c2 * (2.0f * dot - nn - dn));
+#pragma unroll
+          for (int k = 0; k < KP; ++k) part[k] = fmaf(av[b][k], kg, part[k]);
+          const int back = ring_sub(sn, slot, cap);
+          if (back < L) {
+            const int ir = ring_sub(nr, back, R);
+            const float g = fmaf(cm.wl, dot, cm.wg * kg);
+            s.gram[nr * R + ir] = g;
+            s.gram[(nr + R) * R + ir] = g;
+            s.gram[ir * R + nr] = g;
+            s.gram[(ir + R) * R + nr] = g;
+          }
+          const int mv = n - back - evlo;
+          if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
+        }
       }
     }
-    {
-      constexpr int SH = KP == 1 ? 6 : KP == 2 ? 5 : KP == 4 ? 4 : KP == 8 ? 3 : 2;
-      const float v = wave_reduce_scatter<KP>(part);
-      if ((lane & ((1 << SH) - 1)) == 0) s.part[wave * KP + (lane >> SH)] = v;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const float v = wave_sum_to_last(part[k]);
+      if (lane == 63) s.part[wave * KP + k] = v;
     }
     __syncthreads();
 
@@ -369,33 +377,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 
     // ------------------------------------------------------------ phase D
     const float* cbase = s.c + (nw + W) * KP;       // member n - q at cbase - q * KP
-    {
-      // This thread's first prediction update and first linear coefficient
-      // share one sweep over the window (more loads in flight per round).
-      const int t = tid;
-      const bool has_e = t < L * KP && (t % KP) < K;
-      const bool has_w = wk[0] < KP;
-      const int ep = has_e ? t / KP : 0, ek = has_e ? t % KP : 0;
-      const float* ce = cbase + ek;
-      const float* ge = s.gram + (nr + R) * R + ring_sub(nr, ep, R);
-      const float* cw = cbase + (has_w ? wk[0] : 0);
-      const float* rw = s.rwin + (nr + R) * M2P + wm[0];
-      float e0 = 0.0f, e1 = 0.0f, w0 = 0.0f, w1 = 0.0f;
-      int q = 0;
-      for (; q + 2 <= L; q += 2) {
-        e0 = fmaf(ce[-q * KP], ge[-q * R], e0);
-        w0 = fmaf(cw[-q * KP], rw[-q * M2P], w0);
-        e1 = fmaf(ce[-(q + 1) * KP], ge[-(q + 1) * R], e1);
-        w1 = fmaf(cw[-(q + 1) * KP], rw[-(q + 1) * M2P], w1);
-      }
-      if (q < L) {
-        e0 = fmaf(ce[-q * KP], ge[-q * R], e0);
-        w0 = fmaf(cw[-q * KP], rw[-q * M2P], w0);
-      }
-      if (has_e) s.e[ring_sub(nw, ep, W) * KP + ek] += e0 + e1;
-      if (has_w) wreg[0] = fmaf(cm.wl, w0 + w1, wreg[0]);
-    }
-    for (int t = tid + kThreads; t < L * KP; t += kThreads) {
+    for (int t = tid; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
       if (k >= K) continue;
       const int ir = ring_sub(nr, p, R);
@@ -427,7 +409,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       }
     }
 #pragma unroll
-    for (int u = 1; u < WPT; ++u) {
+    for (int u = 0; u < WPT; ++u) {
       if (wk[u] >= KP) continue;
       const float acc = sweep(cbase + wk[u], KP, s.rwin + (nr + R) * M2P + wm[u], M2P, L);
       wreg[u] = fmaf(cm.wl, acc, wreg[u]);
@@ -449,10 +431,9 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     for (int u = 0; u < SLOTS; ++u) {
       const int slot = tid + kThreads * u;
       if (slot < cap) {
-        float* drow = dict + (size_t)slot * M2;
 #pragma unroll
         for (int mm = 0; mm < M2P; ++mm)
-          if (mm < M2) drow[mm] = dreg[u][mm];
+          if (mm < M2) dict[(size_t)mm * cap + slot] = dreg[u][mm];
         float* arow = alpha + (size_t)slot * K;
 #pragma unroll
         for (int k = 0; k < KP; ++k)
@@ -461,7 +442,8 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     }
   } else {
     // Slots never written (T < cap) are cleared so detection may sum them.
-    for (size_t i = (size_t)T * M2 + tid; i < (size_t)cap * M2; i += kThreads) dict[i] = 0.0f;
+    for (int slot = T + tid; slot < cap; slot += kThreads)
+      for (int m = 0; m < M2; ++m) dict[(size_t)m * cap + slot] = 0.0f;
   }
 #pragma unroll
   for (int u = 0; u < WPT; ++u)

@@ -28,8 +28,9 @@ def oracle_params(p):
 
 
 def oracle_model_to_ring(f, cap):
-    """Place an oracle Filter's dictionary into the library's ring layout
-    (sample n in slot n % cap) as float64 arrays."""
+    """Place an oracle Filter's dictionary into the library's ring (sample n
+    in slot n % cap) as float64 arrays, d [cap][M2] (the library stores its
+    transpose, component-major) and alpha [cap][K]."""
     M2, K = f.M2, f.K
     d = np.zeros((cap, M2))
     a = np.zeros((cap, K))
@@ -40,7 +41,9 @@ def oracle_model_to_ring(f, cap):
 
 
 def ring_to_oracle_model(dict_, alpha, w, sigma2, size):
-    """Library ring arrays -> oracle Filter (slot order; the sum is order-free)."""
+    """Library ring arrays (dict_ as [cap][M2], i.e. the transpose of the
+    library's component-major array) -> oracle Filter (slot order; the sum is
+    order-free)."""
     f = O.Filter(w.shape[0], w.shape[1], sigma2)
     f.w = np.asarray(w, dtype=np.float64)
     f.dict_vec = np.asarray(dict_[:size], dtype=np.float64)

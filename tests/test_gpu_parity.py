@@ -32,7 +32,7 @@ def announce(msg):
 def test_detect_golden_two_entries():
     fx = json.load(open(os.path.join(GOLDEN, "detect_two_entries.json")))
     m = A.Model(2, 1, 2, DEV, fx["sigma2"])
-    m.dict.copy_(cuda(np.array(fx["dict"], dtype=np.float32)))
+    m.dict.copy_(cuda(np.array(fx["dict"], dtype=np.float32).T))
     m.alpha.copy_(cuda(np.array(fx["alpha"], dtype=np.float32)))
     m.w.copy_(cuda(np.array(fx["w"], dtype=np.float32)))
     m.state.copy_(cuda(np.array([2, 0, 2, 0], dtype=np.int32)))
@@ -63,7 +63,7 @@ def test_detect_only_parity(K, M, P, S, cap, W, mod):
     f = rounded(O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, oracle_params(p)))
     d, al = oracle_model_to_ring(f, cap)
     m = A.Model(2 * M, K, cap, DEV, p.sigma2)
-    m.dict.copy_(cuda(d.astype(np.float32)))
+    m.dict.copy_(cuda(d.astype(np.float32).T))
     m.alpha.copy_(cuda(al.astype(np.float32)))
     m.w.copy_(cuda(f.w.astype(np.float32)))
     m.state.copy_(cuda(np.array([len(f.dict_vec), 0, 2 * P, 0], dtype=np.int32)))
@@ -132,7 +132,7 @@ def test_end_to_end_parity(name):
     scale_w = max(np.abs(f.w).max(), 1e-3)
     assert np.abs(w_gpu - f.w).max() <= REL_TOL * scale_w
     d_ref, a_ref = oracle_model_to_ring(f, p.dict_cap)
-    np.testing.assert_array_equal(m.dict.cpu().numpy(), d_ref.astype(np.float32))
+    np.testing.assert_array_equal(m.dict.cpu().numpy().T, d_ref.astype(np.float32))
     if p.w_gauss > 0:
         scale_a = max(np.abs(a_ref).max(), 1e-3)
         assert np.abs(m.alpha.cpu().numpy() - a_ref).max() <= REL_TOL * scale_a
