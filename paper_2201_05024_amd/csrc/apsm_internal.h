@@ -91,8 +91,9 @@ hipError_t launch_train(const TrainArgs& a, hipStream_t stream);
 // Heterogeneous training: workgroup b runs jobs[b] (device table of n jobs,
 // each with its variant set by train_variant) with lds_bytes of dynamic LDS
 // (the largest train_lds_bytes of the jobs).
-int train_variant(int M2, int K, int cap);
-size_t train_lds_bytes(int W, int M2, int K);
+bool train_in_table(int M2);              // shapes the table launch holds
+int train_variant(int M2, int K, int W, int cap);
+size_t train_lds_bytes(int W, int M2, int K, int cap);
 hipError_t launch_train_table(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
                               hipStream_t stream);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t stream);

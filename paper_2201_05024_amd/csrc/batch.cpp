@@ -30,6 +30,7 @@ struct apsm_batch {
   std::vector<apsm::DetJob> djobs;
   std::vector<int2> ditems;
   std::vector<int> plain;            // items detected with their own launch
+  std::vector<int> train_plain;      // items trained with their own launch
   size_t off_t = 0, off_p = 0, off_d = 0, off_i = 0, off_c = 0, bytes = 0;
   unsigned char* ws = nullptr;       // bound workspace (device)
   bool persistent = true;
@@ -102,6 +103,10 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tcost[a] > tcost[c]; });
   for (int i : order) {
     const auto& it = b.items[i];
+    if (!train_in_table(it.model.M2)) {
+      b.train_plain.push_back(i);
+      continue;
+    }
     TrainJob j{};
     j.rx = it.rx_pilot;
     j.sym = it.sym_pilot;
@@ -114,9 +119,9 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
     j.K = it.model.K;
     j.cap = it.model.dict_cap;
     j.c2 = kLog2e / (2.0f * it.sigma2);
-    j.variant = train_variant(j.M2, j.K, j.cap);
+    j.variant = train_variant(j.M2, j.K, p->window, j.cap);
     b.tjobs.push_back(j);
-    b.train_lds = std::max(b.train_lds, train_lds_bytes(p->window, j.M2, j.K));
+    b.train_lds = std::max(b.train_lds, train_lds_bytes(p->window, j.M2, j.K, j.cap));
   }
 
   // packing and detection
@@ -254,6 +259,25 @@ int apsm_batch_train(const apsm_batch_t* b, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_train_table(at<TrainJob>(b, b->off_t), (int)b->tjobs.size(), b->cm, b->train_lds, s);
   if (e == hipSuccess) e = launch_pack_model_batch(at<PackJob>(b, b->off_p), (int)b->pjobs.size(), b->pack_max_cap, s);
+  for (size_t q = 0; q < b->train_plain.size() && e == hipSuccess; ++q) {
+    // shapes outside the table kernel (2M > 64): one launch each, no packed form
+    const auto& it = b->items[b->train_plain[q]];
+    TrainArgs a{};
+    a.cm = b->cm;
+    a.rx = it.rx_pilot;
+    a.sym = it.sym_pilot;
+    a.dict[0] = it.model.dict;
+    a.alpha[0] = it.model.alpha;
+    a.w[0] = it.model.w;
+    a.state[0] = it.model.state;
+    a.n_inst = 1;
+    a.P = it.P;
+    a.M2 = it.model.M2;
+    a.K = it.model.K;
+    a.cap = it.model.dict_cap;
+    a.c2 = kLog2e / (2.0f * it.sigma2);
+    e = launch_train(a, s);
+  }
   return hip_status(e);
 }
 

@@ -34,7 +34,7 @@
 namespace apsm {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 
 // Sum over the 64 lanes of a wave; the result is valid in lane 63.  Six
@@ -73,6 +73,7 @@ struct Lds {
   float* aev;    // [KP]     coefficients of the evicted entry
   float* omega;  // [W]      position weights
   float* qden;   // [W+1]    prefix sums of omega
+  float* alds;   // [KP][cap] Gaussian coefficients, k-major (model-buffer path with SLOTS == 0)
 };
 
 __host__ __device__ inline size_t lds_floats(int W, int KP, int M2P) {
@@ -80,6 +81,9 @@ __host__ __device__ inline size_t lds_floats(int W, int KP, int M2P) {
   return 2 * R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 4 * (size_t)W * KP + W +
          2 * R * M2P + kWaves * KP + KP + W + (W + 1);
 }
+
+// LDS budget of one training workgroup (one per CU; static LDS aside).
+constexpr size_t kLdsFloatsMax = 36864;     // 144 KiB
 
 __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
   Lds s;
@@ -95,7 +99,8 @@ __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
   s.part = p; p += kWaves * KP;
   s.aev = p; p += KP;
   s.omega = p; p += W;
-  s.qden = p;
+  s.qden = p; p += W + 1;
+  s.alds = p;
   return s;
 }
 
@@ -187,8 +192,11 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
       for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
     }
+  } else if constexpr (SLOTS == 0) {
+    // Dictionary in the model buffer, coefficients in LDS; start from an empty one.
+    for (int i = tid; i < cap * KP; i += kThreads) s.alds[i] = 0.0f;
   } else {
-    // Model buffers hold the dictionary; start from an empty one.
+    // Dictionary and coefficients in the model buffers; start from an empty one.
     for (size_t i = tid; i < (size_t)cap * K; i += kThreads) alpha[i] = 0.0f;
   }
   if (tid == 0) block_flags = 0;
@@ -279,45 +287,69 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         }
       }
     } else {
-      // Model-buffer path: SB of this thread's slots at a time, every
-      // component of each loaded before any is used, so that SB * M2P loads
-      // are in flight at once (the dictionary is component-major: lanes read
+      // Model-buffer path: SB of this thread's slots at a time, MB components
+      // of each loaded before any is used, so that up to 64 loads are in
+      // flight at once (the dictionary is component-major: lanes read
       // consecutive slots, coalesced).
-      constexpr int SB = M2P >= 128 ? 1 : M2P >= 64 ? 2 : 4;
+      constexpr int SB = M2P >= 64 ? 1 : 64 / M2P;
+      constexpr int MB = M2P >= 64 ? 64 : M2P;
       const int nslot = (n + 1 < cap ? n + 1 : cap);        // slots in use after the append
       if (tid == (sn & (kThreads - 1))) {                   // append (and evict)
-        float* arow = alpha + (size_t)sn * K;
-        if (evicting)
-          for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
+        if constexpr (SLOTS == 0) {
+          if (evicting)
+            for (int k = 0; k < KP; ++k) s.aev[k] = s.alds[k * cap + sn];
+          for (int k = 0; k < KP; ++k) s.alds[k * cap + sn] = 0.0f;
+        } else {
+          float* arow = alpha + (size_t)sn * K;
+          if (evicting)
+            for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
+          for (int k = 0; k < K; ++k) arow[k] = 0.0f;
+        }
         for (int m = 0; m < M2; ++m) dict[(size_t)m * cap + sn] = rrow[m];
-        for (int k = 0; k < K; ++k) arow[k] = 0.0f;
       }
       for (int base = tid; base < nslot; base += SB * kThreads) {
-        float dv[SB][M2P];
-        float av[SB][KP];
+        float dot4[SB][4], dn4[SB][4], av[SB][KP];
 #pragma unroll
         for (int b = 0; b < SB; ++b) {
           const int slot = base + b * kThreads;
           const bool ok = slot < nslot;
-          const float* dcol = dict + (ok ? slot : 0);
 #pragma unroll
-          for (int m = 0; m < M2P; ++m) dv[b][m] = (ok && m < M2) ? dcol[(size_t)m * cap] : 0.0f;
-          const float* arow = alpha + (size_t)(ok ? slot : 0) * K;
+          for (int q = 0; q < 4; ++q) { dot4[b][q] = 0.0f; dn4[b][q] = 0.0f; }
+          if constexpr (SLOTS == 0) {
 #pragma unroll
-          for (int k = 0; k < KP; ++k) av[b][k] = (ok && k < K) ? arow[k] : 0.0f;
+            for (int k = 0; k < KP; ++k) av[b][k] = ok ? s.alds[k * cap + slot] : 0.0f;
+          } else {
+            const float* arow = alpha + (size_t)(ok ? slot : 0) * K;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) av[b][k] = (ok && k < K) ? arow[k] : 0.0f;
+          }
+        }
+#pragma unroll 1
+        for (int m0 = 0; m0 < M2P; m0 += MB) {
+          float dv[SB][MB];
+#pragma unroll
+          for (int b = 0; b < SB; ++b) {
+            const int slot = base + b * kThreads;
+            const bool ok = slot < nslot;
+            const float* dcol = dict + (ok ? slot : 0);
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+              dv[b][m] = (ok && m0 + m < M2) ? dcol[(size_t)(m0 + m) * cap] : 0.0f;
+          }
+#pragma unroll
+          for (int b = 0; b < SB; ++b)
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+              dot4[b][m & 3] = fmaf(rrow[m0 + m], dv[b][m], dot4[b][m & 3]);
+              dn4[b][m & 3] = fmaf(dv[b][m], dv[b][m], dn4[b][m & 3]);
+            }
         }
 #pragma unroll
         for (int b = 0; b < SB; ++b) {
           const int slot = base + b * kThreads;
           if (slot >= nslot) continue;
-          float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f}, n4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-          for (int m = 0; m < M2P; ++m) {
-            d4[m & 3] = fmaf(rrow[m], dv[b][m], d4[m & 3]);
-            n4[m & 3] = fmaf(dv[b][m], dv[b][m], n4[m & 3]);
-          }
-          const float dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-          const float dn = (n4[0] + n4[1]) + (n4[2] + n4[3]);
+          const float dot = (dot4[b][0] + dot4[b][1]) + (dot4[b][2] + dot4[b][3]);
+          const float dn = (dn4[b][0] + dn4[b][1]) + (dn4[b][2] + dn4[b][3]);
           const float kg = __builtin_amdgcn_exp2f(j.c2 * (2.0f * dot - nn - dn));
 #pragma unroll
           for (int k = 0; k < KP; ++k) part[k] = fmaf(av[b][k], kg, part[k]);
@@ -404,8 +436,12 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         const int slot = ring_sub(sn, q, cap);
         if ((slot & (kThreads - 1)) != tid) continue;
         const float* cj = cbase - q * KP;
-        float* arow = alpha + (size_t)slot * K;
-        for (int k = 0; k < K; ++k) arow[k] = fmaf(cj[k], cm.wg, arow[k]);
+        if constexpr (SLOTS == 0) {
+          for (int k = 0; k < KP; ++k) s.alds[k * cap + slot] = fmaf(cj[k], cm.wg, s.alds[k * cap + slot]);
+        } else {
+          float* arow = alpha + (size_t)slot * K;
+          for (int k = 0; k < K; ++k) arow[k] = fmaf(cj[k], cm.wg, arow[k]);
+        }
       }
     }
 #pragma unroll
@@ -444,6 +480,11 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     // Slots never written (T < cap) are cleared so detection may sum them.
     for (int slot = T + tid; slot < cap; slot += kThreads)
       for (int m = 0; m < M2; ++m) dict[(size_t)m * cap + slot] = 0.0f;
+    if constexpr (SLOTS == 0)
+      for (int i = tid; i < cap * K; i += kThreads) {
+        const int slot = i / K, k = i - slot * K;
+        alpha[i] = s.alds[k * cap + slot];
+      }
   }
 #pragma unroll
   for (int u = 0; u < WPT; ++u)
@@ -480,47 +521,58 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   train_body<M2P, KP, SLOTS>(j, a.cm, lds_raw, &block_flags);
 }
 
-// Register-resident dictionary slots per thread for a capacity: SLOTS * M2P
-// dictionary floats stay in registers when that is at most 128; larger
-// dictionaries live in the model buffers (SLOTS = 0).
-__host__ __device__ constexpr int slots_for(int M2P, int cap) {
-  const int need = (cap + kThreads - 1) / kThreads;
-  const int s = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
-  return (s > 0 && s * M2P <= 128) ? s : 0;
-}
-
+// Specialisation for a shape: SLOTS > 0 keeps SLOTS dictionary slots per
+// thread in registers (SLOTS * (M2P + KP) <= 128 floats); SLOTS = 0 keeps
+// the dictionary in the model buffer and the coefficients in LDS; SLOTS = -1
+// keeps both in the model buffers (capacities whose coefficients do not fit
+// the LDS budget).
 __host__ __device__ constexpr int kp_for(int K) { return K <= 4 ? 4 : K <= 8 ? 8 : 16; }
 __host__ __device__ constexpr int m2p_for(int M2) { return M2 <= 16 ? 16 : M2 <= 32 ? 32 : M2 <= 64 ? 64 : 128; }
 
+__host__ __device__ inline int slots_for(int M2P, int KP, int W, int cap) {
+  const int need = (cap + kThreads - 1) / kThreads;
+  const int s = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
+  // dictionary plus coefficient registers of the slots within 128 per thread
+  // (two waves per SIMD at 512 threads leave 256 registers per thread)
+  if (s > 0 && s * (M2P + KP) <= 128) return s;
+  return lds_floats(W, KP, M2P) + (size_t)cap * KP <= kLdsFloatsMax ? 0 : -1;
+}
+
+__host__ __device__ inline size_t lds_bytes_for(int W, int KP, int M2P, int slots, int cap) {
+  return (lds_floats(W, KP, M2P) + (slots == 0 ? (size_t)cap * KP : 0)) * sizeof(float);
+}
+
 // Every specialisation (M2P, KP, SLOTS) with its variant number.
 #define APSM_TRAIN_VARIANTS_M(X, base, M2P, KP)                                    \
-  X(base + 0, M2P, KP, 0) X(base + 1, M2P, KP, 1) X(base + 2, M2P, KP, 2)          \
-  X(base + 3, M2P, KP, 4) X(base + 4, M2P, KP, 8)
+  X(base + 0, M2P, KP, -1) X(base + 1, M2P, KP, 0) X(base + 2, M2P, KP, 1)         \
+  X(base + 3, M2P, KP, 2) X(base + 4, M2P, KP, 4) X(base + 5, M2P, KP, 8)
 #define APSM_TRAIN_VARIANTS(X)                                                      \
-  APSM_TRAIN_VARIANTS_M(X, 0, 16, 4) APSM_TRAIN_VARIANTS_M(X, 5, 16, 8)            \
-  APSM_TRAIN_VARIANTS_M(X, 10, 16, 16) APSM_TRAIN_VARIANTS_M(X, 15, 32, 4)         \
-  APSM_TRAIN_VARIANTS_M(X, 20, 32, 8) APSM_TRAIN_VARIANTS_M(X, 25, 32, 16)         \
-  APSM_TRAIN_VARIANTS_M(X, 30, 64, 4) APSM_TRAIN_VARIANTS_M(X, 35, 64, 8)          \
-  APSM_TRAIN_VARIANTS_M(X, 40, 64, 16) APSM_TRAIN_VARIANTS_M(X, 45, 128, 4)        \
-  APSM_TRAIN_VARIANTS_M(X, 50, 128, 8) APSM_TRAIN_VARIANTS_M(X, 55, 128, 16)
+  APSM_TRAIN_VARIANTS_M(X, 0, 16, 4) APSM_TRAIN_VARIANTS_M(X, 6, 16, 8)            \
+  APSM_TRAIN_VARIANTS_M(X, 12, 16, 16) APSM_TRAIN_VARIANTS_M(X, 18, 32, 4)         \
+  APSM_TRAIN_VARIANTS_M(X, 24, 32, 8) APSM_TRAIN_VARIANTS_M(X, 30, 32, 16)         \
+  APSM_TRAIN_VARIANTS_M(X, 36, 64, 4) APSM_TRAIN_VARIANTS_M(X, 42, 64, 8)          \
+  APSM_TRAIN_VARIANTS_M(X, 48, 64, 16) APSM_TRAIN_VARIANTS_M(X, 54, 128, 4)        \
+  APSM_TRAIN_VARIANTS_M(X, 60, 128, 8) APSM_TRAIN_VARIANTS_M(X, 66, 128, 16)
 
 __host__ __device__ constexpr int variant_of(int M2P, int KP, int SLOTS) {
   const int mi = M2P == 16 ? 0 : M2P == 32 ? 1 : M2P == 64 ? 2 : 3;
   const int ki = KP == 4 ? 0 : KP == 8 ? 1 : 2;
-  const int si = SLOTS == 0 ? 0 : SLOTS == 1 ? 1 : SLOTS == 2 ? 2 : SLOTS == 4 ? 3 : 4;
-  return (mi * 3 + ki) * 5 + si;
+  const int si = SLOTS < 0 ? 0 : SLOTS == 0 ? 1 : SLOTS == 1 ? 2 : SLOTS == 2 ? 3 : SLOTS == 4 ? 4 : 5;
+  return (mi * 3 + ki) * 6 + si;
 }
 
 // The table kernel holds the register-resident specialisations only where
 // they fit the register file on their own (no spill space needed); other
-// jobs take the model-buffer path (SLOTS = 0).  One function holding the
-// heavier ones as well would spill for all of them.
+// jobs take the model-buffer path.  One function holding the heavier ones as
+// well would spill for all of them.
 __host__ __device__ constexpr bool in_table(int M2P, int KP, int SLOTS) {
-  return SLOTS == 0 || (SLOTS * (M2P + KP) <= 128 && !(M2P == 64 && KP == 16));
+  return SLOTS <= 0 || (SLOTS * (M2P + KP) <= 128 && !(M2P == 64 && KP == 16));
 }
 
-// Detectors of any shapes, one job per workgroup from a device table; each
-// job runs the specialisation its variant names.
+// Detectors of shapes with 2M <= 64, one job per workgroup from a device
+// table; each job runs the specialisation its variant names.  (The 2M = 128
+// specialisations, held in the same function, would make it spill for every
+// job: such detectors are trained by their own launches.)
 __global__ __launch_bounds__(kThreads) void train_table_kernel(const TrainJob* jobs, TrainCommon cm) {
   extern __shared__ float lds_raw[];
   __shared__ int block_flags;
@@ -528,7 +580,7 @@ __global__ __launch_bounds__(kThreads) void train_table_kernel(const TrainJob* j
   switch (j.variant) {
 #define APSM_TRAIN_CASE(id, M2P, KP, SLOTS)                                         \
   case id:                                                                          \
-    if constexpr (SLOTS * M2P <= 128 && in_table(M2P, KP, SLOTS)) train_body<M2P, KP, SLOTS>(j, cm, lds_raw, &block_flags); \
+    if constexpr (M2P <= 64 && in_table(M2P, KP, SLOTS)) train_body<M2P, KP, SLOTS>(j, cm, lds_raw, &block_flags); \
     break;
     APSM_TRAIN_VARIANTS(APSM_TRAIN_CASE)
 #undef APSM_TRAIN_CASE
@@ -539,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void train_table_kernel(const TrainJob* j
 
 template <int M2P, int KP, int SLOTS>
 hipError_t launch_one(const TrainArgs& a, hipStream_t stream) {
-  const size_t bytes = lds_floats(a.cm.W, KP, M2P) * sizeof(float);
+  const size_t bytes = lds_bytes_for(a.cm.W, KP, M2P, SLOTS, a.cap);
   auto kern = train_kernel<M2P, KP, SLOTS>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -550,14 +602,15 @@ hipError_t launch_one(const TrainArgs& a, hipStream_t stream) {
 
 template <int M2P, int KP>
 hipError_t pick_slots(const TrainArgs& a, hipStream_t stream) {
-  switch (slots_for(M2P, a.cap)) {
-    case 1: return launch_one<M2P, KP, 1>(a, stream);
-    case 2: if constexpr (2 * M2P <= 128) return launch_one<M2P, KP, 2>(a, stream); break;
-    case 4: if constexpr (4 * M2P <= 128) return launch_one<M2P, KP, 4>(a, stream); break;
-    case 8: if constexpr (8 * M2P <= 128) return launch_one<M2P, KP, 8>(a, stream); break;
+  switch (slots_for(M2P, KP, a.cm.W, a.cap)) {
+    case 1: if constexpr (1 * (M2P + KP) <= 128) return launch_one<M2P, KP, 1>(a, stream); break;
+    case 2: if constexpr (2 * (M2P + KP) <= 128) return launch_one<M2P, KP, 2>(a, stream); break;
+    case 4: if constexpr (4 * (M2P + KP) <= 128) return launch_one<M2P, KP, 4>(a, stream); break;
+    case 8: if constexpr (8 * (M2P + KP) <= 128) return launch_one<M2P, KP, 8>(a, stream); break;
+    case 0: return launch_one<M2P, KP, 0>(a, stream);
     default: break;
   }
-  return launch_one<M2P, KP, 0>(a, stream);
+  return launch_one<M2P, KP, -1>(a, stream);
 }
 
 template <int M2P>
@@ -577,14 +630,23 @@ hipError_t launch_train(const TrainArgs& a, hipStream_t stream) {
   return hipErrorInvalidValue;
 }
 
-int train_variant(int M2, int K, int cap) {
+// Specialisation of the table kernel for a shape (register-resident slots
+// that the table does not hold take the model-buffer path).
+static int table_slots(int M2, int K, int W, int cap) {
   const int M2P = m2p_for(M2), KP = kp_for(K);
-  const int slots = slots_for(M2P, cap);
-  return variant_of(M2P, KP, in_table(M2P, KP, slots) ? slots : 0);
+  const int slots = slots_for(M2P, KP, W, cap);
+  if (in_table(M2P, KP, slots)) return slots;
+  return lds_floats(W, KP, M2P) + (size_t)cap * KP <= kLdsFloatsMax ? 0 : -1;
 }
 
-size_t train_lds_bytes(int W, int M2, int K) {
-  return lds_floats(W, kp_for(K), m2p_for(M2)) * sizeof(float);
+bool train_in_table(int M2) { return M2 <= 64; }
+
+int train_variant(int M2, int K, int W, int cap) {
+  return variant_of(m2p_for(M2), kp_for(K), table_slots(M2, K, W, cap));
+}
+
+size_t train_lds_bytes(int W, int M2, int K, int cap) {
+  return lds_bytes_for(W, kp_for(K), m2p_for(M2), table_slots(M2, K, W, cap), cap);
 }
 
 hipError_t launch_train_table(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
