@@ -326,22 +326,27 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         }
 #pragma unroll 1
         for (int m0 = 0; m0 < M2P; m0 += MB) {
+          // Unconditional loads (clamped addresses) so that they issue back to
+          // back; padded components (m >= M2) are masked out after the load,
+          // and slots past the ones in use are discarded below.
           float dv[SB][MB];
 #pragma unroll
           for (int b = 0; b < SB; ++b) {
             const int slot = base + b * kThreads;
-            const bool ok = slot < nslot;
-            const float* dcol = dict + (ok ? slot : 0);
+            const float* dcol = dict + (slot < nslot ? slot : 0);
 #pragma unroll
-            for (int m = 0; m < MB; ++m)
-              dv[b][m] = (ok && m0 + m < M2) ? dcol[(size_t)(m0 + m) * cap] : 0.0f;
+            for (int m = 0; m < MB; ++m) {
+              const int mm = m0 + m < M2 ? m0 + m : M2 - 1;
+              dv[b][m] = dcol[(size_t)mm * cap];
+            }
           }
 #pragma unroll
           for (int b = 0; b < SB; ++b)
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
-              dot4[b][m & 3] = fmaf(rrow[m0 + m], dv[b][m], dot4[b][m & 3]);
-              dn4[b][m & 3] = fmaf(dv[b][m], dv[b][m], dn4[b][m & 3]);
+              const float d = m0 + m < M2 ? dv[b][m] : 0.0f;
+              dot4[b][m & 3] = fmaf(rrow[m0 + m], d, dot4[b][m & 3]);
+              dn4[b][m & 3] = fmaf(d, d, dn4[b][m & 3]);
             }
         }
 #pragma unroll
@@ -396,6 +401,17 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         const float kjj = fmaf(cm.wl, s.nrm[jw], cm.wg);
         const float beta = kjj > 0.0f ? -soft_threshold(x, cm.eps) / kjj : 0.0f;
         c = qscale * s.omega[p] * beta;
+        if constexpr (SLOTS <= 0) {
+          // Gaussian coefficient of member n - p (its dictionary slot), one
+          // (member, user) pair per thread; the barrier below orders it
+          // before every later read.
+          const int slot = ring_sub(sn, p, cap);
+          if constexpr (SLOTS == 0) {
+            s.alds[k * cap + slot] = fmaf(c, cm.wg, s.alds[k * cap + slot]);
+          } else {
+            alpha[(size_t)slot * K + k] = fmaf(c, cm.wg, alpha[(size_t)slot * K + k]);
+          }
+        }
       }
       s.c[jw * KP + k] = c;
       s.c[(jw + W) * KP + k] = c;
@@ -427,20 +443,6 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
             for (int k = 0; k < KP; ++k) areg[u][k] = fmaf(cj[k], cm.wg, areg[u][k]);
           }
-        }
-      }
-    } else {
-      // The owner of a slot updates it, so that its own reads in the next
-      // phase A see the new value without a barrier.
-      for (int q = 0; q < L; ++q) {
-        const int slot = ring_sub(sn, q, cap);
-        if ((slot & (kThreads - 1)) != tid) continue;
-        const float* cj = cbase - q * KP;
-        if constexpr (SLOTS == 0) {
-          for (int k = 0; k < KP; ++k) s.alds[k * cap + slot] = fmaf(cj[k], cm.wg, s.alds[k * cap + slot]);
-        } else {
-          float* arow = alpha + (size_t)slot * K;
-          for (int k = 0; k < K; ++k) arow[k] = fmaf(cj[k], cm.wg, arow[k]);
         }
       }
     }
