@@ -33,6 +33,29 @@ METRIC = ("detected symbols/s and kernel evals/s vs roofline at oracle SER; "
 PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 
+# HBM bytes per launch of detect_f16_kernel<32,6> on this workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 256 MiB device copy
+# (profiles/detect_f16_realistic_slot_counters.md).  Valid only for the kernel
+# sources they were taken with; reported as null otherwise.
+MEASURED_TRAFFIC = {
+    "bytes": (138944 + 55296) * 1024,
+    "sources": {"paper_2201_05024_amd/csrc/detect_f16.h": "2b5f97b6a6a665bb0de93898fcacb970bd49cda8",
+                "paper_2201_05024_amd/csrc/detect_f16_m32.hip": "d4dbc3a03f2d61d0eb05e76f679e0ec7b04f4b6c"},
+}
+
+
+def measured_traffic():
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel, digest in MEASURED_TRAFFIC["sources"].items():
+        try:
+            with open(os.path.join(root, rel), "rb") as fh:
+                if hashlib.sha1(fh.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return MEASURED_TRAFFIC["bytes"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -49,6 +72,8 @@ def parse():
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched mixed-shape workload")
+    ap.add_argument("--serial", action="store_true",
+                    help="train then detect within each step (no overlap of consecutive steps)")
     ap.add_argument("--batched-steps", type=int, default=5)
     return ap.parse_args()
 
@@ -209,48 +234,87 @@ def main():
     sym_p = torch.from_numpy(np.stack([i.sym_pilot for i in insts])).to(dev)
     rx_d = [torch.from_numpy(i.rx_data).to(dev) for i in insts]
     truth = [torch.from_numpy(i.truth).to(dev) for i in insts]
-    models = [A.Model(M2, K, params.dict_cap, dev, params.sigma2) for _ in insts]
+    # Two model sets: in the pipelined schedule the detectors of step k are
+    # trained while the detection of step k - 1 runs on the other set.
+    models = [[A.Model(M2, K, params.dict_cap, dev, params.sigma2) for _ in insts] for _ in range(2)]
     soft = [torch.empty((S, K, 2), dtype=torch.float32, device=dev) for _ in insts]
     hard = [torch.empty((S, K), dtype=torch.uint8, device=dev) for _ in insts]
     errs = [torch.zeros(K, dtype=torch.int64, device=dev) for _ in insts]
-    main_s = torch.cuda.current_stream()
+    s_train = torch.cuda.Stream()
+    s_det = torch.cuda.Stream()
+    trained = [torch.cuda.Event(), torch.cuda.Event()]
+    detected = [torch.cuda.Event(), torch.cuda.Event()]
     torch.cuda.synchronize()
 
     det_events = []
 
-    def step(record):
-        # the four trainings run concurrently in one launch (one workgroup each)
-        A.train_batched(rx_p, sym_p, params, models=models, stream=main_s)
+    def detect_set(ms, stream, record):
         for e in errs:
             e.zero_()
         for i in range(len(insts)):
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(main_s)
-            A.detect(models[i], rx_d[i], modulation="qpsk", truth=truth[i], soft=soft[i],
-                     hard=hard[i], errors=errs[i], stream=main_s)
+                e0.record(stream)
+            A.detect(ms[i], rx_d[i], modulation="qpsk", truth=truth[i], soft=soft[i],
+                     hard=hard[i], errors=errs[i], stream=stream)
             if record:
-                e1.record(main_s)
+                e1.record(stream)
                 det_events.append((e0, e1))
 
+    def step(k, record):
+        cur, prev = k % 2, (k + 1) % 2
+        if args.serial:
+            with torch.cuda.stream(s_det):
+                A.train_batched(rx_p, sym_p, params, models=models[cur], stream=s_det)
+                detect_set(models[cur], s_det, record)
+            return
+        # the four trainings of step k (one launch) beside the detection of step k - 1
+        with torch.cuda.stream(s_train):
+            s_train.wait_event(detected[cur])
+            A.train_batched(rx_p, sym_p, params, models=models[cur], stream=s_train)
+            trained[cur].record(s_train)
+        with torch.cuda.stream(s_det):
+            s_det.wait_event(trained[prev])
+            detect_set(models[prev], s_det, record)
+            detected[prev].record(s_det)
+
     log(f"[bench] warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step(False)
+    # the set detected first in the timed region is trained here
+    with torch.cuda.stream(s_train):
+        A.train_batched(rx_p, sym_p, params, models=models[1], stream=s_train)
+        trained[1].record(s_train)
+    for k in range(args.warmup):
+        step(k, False)
     torch.cuda.synchronize()
 
     # training alone, for the report
     t_ev0, t_ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_ev0.record(main_s)
-    A.train_batched(rx_p, sym_p, params, models=models, stream=main_s)
-    t_ev1.record(main_s)
+    t_ev0.record(s_train)
+    A.train_batched(rx_p, sym_p, params, models=models[0], stream=s_train)
+    t_ev1.record(s_train)
     torch.cuda.synchronize()
     train_ms = t_ev0.elapsed_time(t_ev1)
+    # the serialized step (train, then detect) for the report
+    t0 = time.perf_counter()
+    for _ in range(3):
+        with torch.cuda.stream(s_det):
+            A.train_batched(rx_p, sym_p, params, models=models[0], stream=s_det)
+            detect_set(models[0], s_det, False)
+    torch.cuda.synchronize()
+    serial_ms = (time.perf_counter() - t0) / 3 * 1e3
+    # re-arm the pipeline: set 1 trained, set 0 free
+    with torch.cuda.stream(s_train):
+        A.train_batched(rx_p, sym_p, params, models=models[1], stream=s_train)
+        trained[1].record(s_train)
+    with torch.cuda.stream(s_det):
+        detected[0].record(s_det)
+    torch.cuda.synchronize()
 
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
+    for k in range(args.steps):
+        step(k, True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log("[bench] timed region done")
@@ -300,7 +364,8 @@ def main():
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "peak_with_packed_fp32": 2 * PEAK_FP32_VALU_TFLOPS,
             "per_launch": {"real_vectors": S_r, "dictionary": D,
                            "kernel_evals": evals_per_launch,
                            "valu_flops_per_eval": valu_flops_per_eval,
@@ -312,6 +377,11 @@ def main():
             "kernel_evals_per_s": evals_per_launch / det_avg_s,
         },
         "train_ms_4_instances_one_launch": train_ms,
+        "schedule": ("serial: train then detect within each step" if args.serial else
+                     "pipelined: the trainings of step k (one launch, 4 CUs) run beside the detection "
+                     "of step k-1 on a second stream; every step trains 4 detectors and detects "
+                     "4 x 1048576 symbols"),
+        "ms_per_step_serialized": serial_ms,
         "train_steps_per_instance": 2 * P,
         "ser_gpu": ser,
     }
