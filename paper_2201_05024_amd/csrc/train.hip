@@ -19,6 +19,10 @@
 //   -- barrier --
 //   D  running predictions e_i += sum_j c_j K(r_j, r_i) for the members that
 //      stay, alpha[slot(j)] += c_j wG (slot owners), w_k += wL sum_j c_j r_j.
+//      The two sums over members are small dense contractions (Gram block
+//      times coefficients, coefficients times member vectors) and run as
+//      16 x 16 tiles of v_mfma_f32_16x16x4_f32; the linear weights stay in
+//      the accumulator registers of their tiles for the whole training.
 //
 // The window predictions are thus updated incrementally (D Gaussian
 // evaluations per step instead of |J_n| * D); this is exact up to rounding
@@ -57,15 +61,18 @@ __device__ __forceinline__ float soft_threshold(float x, float eps) {
 
 // Shared-memory layout, sized at launch from W, K and M2P.  Rings indexed by
 // the training index modulo W (or R = W + 1) hold the window members.  The
-// rings that phase D sweeps are stored twice (rows r and r + size), so that
-// the L newest members are the contiguous rows base - L + 1 .. base with
-// base = (n mod size) + size: the sweeps run with constant strides and no
-// wrap-around arithmetic.
+// rings that phase D reads member by member are stored twice (positions r
+// and r + size), so that the L newest members sit at the contiguous
+// positions base - L + 1 .. base with base = (n mod size) + size: member q
+// is at a constant offset from a per-lane base, with no wrap-around
+// arithmetic.
+constexpr int CS = 16;   // row stride of the coefficient ring (users KP..15 stay zero)
+
 struct Lds {
-  float* gram;   // [2R][R]  K(r_j, r_i) of window members (rows doubled)
+  float* gram;   // [R][2R]  K(r_j, r_i) of window members (columns doubled)
   float* evkr;   // [W][W-1] kappa_G(r_j, d_v) for the entries v evicted while j is in the window
   float* e;      // [W][KP]  running predictions f(r_j)
-  float* c;      // [2W][KP] mu q_j beta_jk of the current step (rows doubled)
+  float* c;      // [2W][CS] mu q_j beta_jk of the current step (rows doubled)
   float* bwin;   // [W][KP]  training symbols b_j of the window members
   float* nrm;    // [W]      ||r_j||^2
   float* rwin;   // [2R][M2P] window members' vectors and r_{n+1} (rows doubled)
@@ -78,7 +85,7 @@ struct Lds {
 
 __host__ __device__ inline size_t lds_floats(int W, int KP, int M2P) {
   const size_t R = W + 1;
-  return 2 * R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 4 * (size_t)W * KP + W +
+  return 2 * R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 2 * (size_t)W * KP + 2 * (size_t)W * CS + W +
          2 * R * M2P + kWaves * KP + KP + W + (W + 1);
 }
 
@@ -92,7 +99,7 @@ __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
   s.gram = p; p += 2 * R * R;
   s.evkr = p; p += W * (W > 1 ? W - 1 : 1);
   s.e = p; p += W * KP;
-  s.c = p; p += 2 * W * KP;
+  s.c = p; p += 2 * W * CS;
   s.bwin = p; p += W * KP;
   s.nrm = p; p += W;
   s.rwin = p; p += 2 * R * M2P;
@@ -119,18 +126,62 @@ __device__ __forceinline__ int ring_sub(int a, int b, int mod) {
   return r < 0 ? r + mod : r;
 }
 
-// sum_{q < L} x[-q * xs] * y[-q * ys], eight loads in flight per round.
-__device__ __forceinline__ float sweep(const float* x, int xs, const float* y, int ys, int L) {
-  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-  int q = 0;
-  for (; q + 4 <= L; q += 4) {
-    a0 = fmaf(x[-q * xs], y[-q * ys], a0);
-    a1 = fmaf(x[-(q + 1) * xs], y[-(q + 1) * ys], a1);
-    a2 = fmaf(x[-(q + 2) * xs], y[-(q + 2) * ys], a2);
-    a3 = fmaf(x[-(q + 3) * xs], y[-(q + 3) * ys], a3);
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// NST steps of a member product from member q0 on: every operand load
+// first, then the products, in straight-line code so that the loads issue
+// back to back.  FULL: every member of the block is below L, so the loads
+// are offsets from one per-lane address; otherwise members past L enter as
+// zeros, read at member 0's address.
+template <int SA, int SB, int NST, bool FULL>
+__device__ __forceinline__ floatx4 member_block(floatx4 acc, int q0, int L, int grp, const float* a0,
+                                                const float* b0) {
+  float av[NST], bv[NST];
+  if constexpr (FULL) {
+    const int qlo = q0 + grp + 4 * (NST - 1);
+    const float* pa = a0 - qlo * SA;
+    const float* pb = b0 - qlo * SB;
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+      av[st] = pa[4 * (NST - 1 - st) * SA];
+      bv[st] = pb[4 * (NST - 1 - st) * SB];
+    }
+  } else {
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+      const int q = q0 + 4 * st + grp;
+      const bool ok = q < L;
+      const int qc = ok ? q : 0;
+      const float x = a0[-qc * SA], y = b0[-qc * SB];
+      av[st] = ok ? x : 0.0f;
+      bv[st] = ok ? y : 0.0f;
+    }
   }
-  for (; q < L; ++q) a0 = fmaf(x[-q * xs], y[-q * ys], a0);
-  return (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int st = 0; st < NST; ++st) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st], acc, 0, 0, 0);
+  return acc;
+}
+
+// acc += sum over window members q < L of a0[-q SA] b0[-q SB] on one 16 x 16
+// tile of v_mfma_f32_16x16x4_f32 (a0, b0: this lane's A and B operands for
+// the newest member; lane group grp supplies member 4 step + grp of each
+// step).  Blocks of 8 steps (32 members), or 4 for a remainder of 16 or
+// fewer.
+template <int SA, int SB>
+__device__ __forceinline__ floatx4 member_product(floatx4 acc, int L, int grp, const float* a0,
+                                                  const float* b0) {
+  for (int q0 = 0; q0 < L; q0 += 32) {
+    const int rem = L - q0;
+    if (rem >= 32)
+      acc = member_block<SA, SB, 8, true>(acc, q0, L, grp, a0, b0);
+    else if (rem > 16)
+      acc = member_block<SA, SB, 8, false>(acc, q0, L, grp, a0, b0);
+    else if (rem == 16)
+      acc = member_block<SA, SB, 4, true>(acc, q0, L, grp, a0, b0);
+    else
+      acc = member_block<SA, SB, 4, false>(acc, q0, L, grp, a0, b0);
+  }
+  return acc;
 }
 
 // Training of one detector by one workgroup of kThreads threads.  lds_raw
@@ -139,11 +190,10 @@ template <int M2P, int KP, int SLOTS>
 __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon& cm, float* lds_raw,
                                            int* block_flags_p) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int W = cm.W, R = W + 1, cap = j.cap, K = j.K, M2 = j.M2, M = j.M2 / 2;
   const int T = 2 * j.P;
   const int EVS = W > 1 ? W - 1 : 1;
-  const int KM = K * M2;
   Lds s = carve(lds_raw, W, KP, M2P);
   const float* rx = j.rx;
   const float* sym = j.sym;
@@ -155,10 +205,9 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 
   for (int i = tid; i < W * KP; i += kThreads) {
     s.e[i] = 0.0f;
-    s.c[i] = 0.0f;
-    s.c[i + W * KP] = 0.0f;
     s.bwin[i] = 0.0f;
   }
+  for (int i = tid; i < 2 * W * CS; i += kThreads) s.c[i] = 0.0f;
   if (tid < W) s.omega[tid] = cm.omega[tid];
   if (tid == 0) {
     float acc = 0.0f;
@@ -166,18 +215,19 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     for (int p = 0; p < W; ++p) { acc += cm.omega[p]; s.qden[p + 1] = acc; }
   }
 
-  // Linear coefficients: entry e = k * M2 + m lives in a register of thread
-  // e % kThreads, which both updates it and uses it for f_n(r_n).
-  constexpr int WPT = (KP * M2P + kThreads - 1) / kThreads;
-  float wreg[WPT];
-  int wk[WPT], wm[WPT];
-#pragma unroll
-  for (int u = 0; u < WPT; ++u) {
-    const int e = tid + kThreads * u;
-    wreg[u] = 0.0f;
-    wk[u] = e < KM ? e / M2 : KP;           // KP marks "no entry"
-    wm[u] = e < KM ? e - (e / M2) * M2 : 0;
-  }
+  // Linear coefficients w = wL v, v[k][m] held as matrix-core accumulators:
+  // wave t < M2P/16 holds the 16 x 16 tile of components 16 t .. 16 t + 15
+  // (users 0..15), its lane l and register i holding v[4 (l / 16) + i][16 t +
+  // l % 16].  The wave both updates the tile (phase D) and uses it for
+  // f_n(r_n) (phase A).
+  // The Gram-times-coefficient tiles of phase D go to the waves after them.
+  constexpr int NWT = M2P / 16;
+  const bool wowner = wave < NWT;
+  const int col = lane & 15;                // tile column of this lane
+  const int grp = lane >> 4;                // tile rows 4 grp .. 4 grp + 3 of this lane
+  const int wm = 16 * wave + col;           // component of this lane's weight-tile column
+  const int etile = (wave - NWT) & (kWaves - 1);
+  floatx4 wacc = {0.0f, 0.0f, 0.0f, 0.0f};
 
   // Register-resident slots (SLOTS > 0): slot tid + kThreads * u.
   float dreg[SLOTS > 0 ? SLOTS : 1][M2P];
@@ -243,11 +293,10 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     float part[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) part[k] = 0.0f;
+    if (wowner) {
+      const float rm = cm.wl * rrow[wm];
 #pragma unroll
-    for (int u = 0; u < WPT; ++u) {
-      const float prod = wreg[u] * rrow[wm[u]];
-#pragma unroll
-      for (int k = 0; k < KP; ++k) part[k] += (wk[u] == k) ? prod : 0.0f;
+      for (int k = 0; k < KP; ++k) part[k] += (grp == (k >> 2)) ? wacc[k & 3] * rm : 0.0f;
     }
 
     if constexpr (SLOTS > 0) {
@@ -277,10 +326,10 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
           if (back < L) {
             const int ir = ring_sub(nr, back, R);
             const float g = fmaf(cm.wl, dot, cm.wg * kg);
-            s.gram[nr * R + ir] = g;
-            s.gram[(nr + R) * R + ir] = g;
-            s.gram[ir * R + nr] = g;
-            s.gram[(ir + R) * R + nr] = g;
+            s.gram[nr * 2 * R + ir] = g;
+            s.gram[nr * 2 * R + ir + R] = g;
+            s.gram[ir * 2 * R + nr] = g;
+            s.gram[ir * 2 * R + nr + R] = g;
           }
           const int mv = n - back - evlo;
           if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
@@ -362,10 +411,10 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
           if (back < L) {
             const int ir = ring_sub(nr, back, R);
             const float g = fmaf(cm.wl, dot, cm.wg * kg);
-            s.gram[nr * R + ir] = g;
-            s.gram[(nr + R) * R + ir] = g;
-            s.gram[ir * R + nr] = g;
-            s.gram[(ir + R) * R + nr] = g;
+            s.gram[nr * 2 * R + ir] = g;
+            s.gram[nr * 2 * R + ir + R] = g;
+            s.gram[ir * 2 * R + nr] = g;
+            s.gram[ir * 2 * R + nr + R] = g;
           }
           const int mv = n - back - evlo;
           if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
@@ -413,8 +462,8 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
           }
         }
       }
-      s.c[jw * KP + k] = c;
-      s.c[(jw + W) * KP + k] = c;
+      s.c[jw * CS + k] = c;
+      s.c[(jw + W) * CS + k] = c;
     }
     if (tid < M2P && n + 1 < T) {           // r_{n+1} into its ring row (no member of J_n)
       const int nr1 = nr + 1 == R ? 0 : nr + 1;
@@ -424,13 +473,30 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     __syncthreads();
 
     // ------------------------------------------------------------ phase D
-    const float* cbase = s.c + (nw + W) * KP;       // member n - q at cbase - q * KP
-    for (int t = tid; t < L * KP; t += kThreads) {
-      const int p = t / KP, k = t - p * KP;
-      if (k >= K) continue;
-      const int ir = ring_sub(nr, p, R);
-      const float de = sweep(cbase + k, KP, s.gram + (nr + R) * R + ir, R, L);
-      s.e[ring_sub(nw, p, W) * KP + k] += de;
+    const float* cbase = s.c + (nw + W) * CS;       // member n - q at cbase - q * CS
+    if (wowner) {
+      // v[k][m] += sum_q c_{q,k} r_q[m] with w = wL v: A = coefficients
+      // (rows k), B = member vectors
+      wacc = member_product<CS, M2P>(wacc, L, grp, cbase + col, s.rwin + (nr + R) * M2P + wm);
+    }
+    if (etile < ((L + 15) >> 4)) {
+      // e[i][k] += sum_q K(r_i, r_q) c_{q,k}: A = Gram rows of members
+      // 16 etile .. 16 etile + 15 (columns doubled along the member index
+      // q), B = coefficients
+      const int ia = 16 * etile + col;
+      const float* grow = s.gram + ring_sub(nr, ia < L ? ia : 0, R) * 2 * R + nr + R;
+      floatx4 acc;
+      int eidx[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * etile + 4 * grp + v;
+        eidx[v] = (i < L && col < KP) ? ring_sub(nw, i, W) * KP + col : -1;
+        acc[v] = s.e[eidx[v] >= 0 ? eidx[v] : 0];
+      }
+      acc = member_product<1, CS>(acc, L, grp, grow, cbase + col);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (eidx[v] >= 0) s.e[eidx[v]] = acc[v];
     }
     if constexpr (SLOTS > 0) {
 #pragma unroll
@@ -439,18 +505,12 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         if (slot < cap && slot <= n) {
           const int back = ring_sub(sn, slot, cap);
           if (back < L) {
-            const float* cj = cbase - back * KP;
+            const float* cj = cbase - back * CS;
 #pragma unroll
             for (int k = 0; k < KP; ++k) areg[u][k] = fmaf(cj[k], cm.wg, areg[u][k]);
           }
         }
       }
-    }
-#pragma unroll
-    for (int u = 0; u < WPT; ++u) {
-      if (wk[u] >= KP) continue;
-      const float acc = sweep(cbase + wk[u], KP, s.rwin + (nr + R) * M2P + wm[u], M2P, L);
-      wreg[u] = fmaf(cm.wl, acc, wreg[u]);
     }
     // Phase A of the next step touches only ring rows that no window member
     // of this step uses (the Gram and vector rings have W + 1 rows; the
@@ -488,9 +548,13 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         alpha[i] = s.alds[k * cap + slot];
       }
   }
+  if (wowner) {
 #pragma unroll
-  for (int u = 0; u < WPT; ++u)
-    if (wk[u] < KP) wout[tid + kThreads * u] = wreg[u];
+    for (int v = 0; v < 4; ++v) {
+      const int k = 4 * grp + v;
+      if (k < K && wm < M2) wout[k * M2 + wm] = cm.wl * wacc[v];
+    }
+  }
   if (flags) atomicOr(&block_flags, flags);
   __syncthreads();
   if (tid == 0) {
