@@ -41,17 +41,74 @@ namespace {
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 
-// Sum over the 64 lanes of a wave; the result is valid in lane 63.  Six
-// DPP steps (quad swaps, row mirrors, row broadcasts) that stay in the
-// VALU, with no LDS round trip.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x140, 0xF, 0xF, false);  // row_mirror
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
-  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
-  return v;
+// Wave sums of KP values per lane, scattered over the lanes: afterwards
+// every lane holds the sum over the wave of v[user_of_lane(lane)].  Each
+// exchange level pairs lanes whose indices differ by a fixed xor pattern
+// (7 by row_half_mirror, 1 and 2 by quad_perm, 8 by row_ror:8); the lane
+// keeps half of its values, adds the partner's matching half and sends the
+// other half, so level by level the values per lane halve.  Levels past
+// one value per lane add the partner's value whole; the four 16-lane rows
+// are then summed by the gfx950 row-swap permutes.
+template <int N>
+__device__ __forceinline__ void scatter_level(float* v, bool upper, int ctrl) {
+#pragma unroll
+  for (int j = 0; j < N / 2; ++j) {
+    const float keep = upper ? v[j + N / 2] : v[j];
+    const float send = upper ? v[j] : v[j + N / 2];
+    float got;
+    switch (ctrl) {
+      case 0x141: got = __builtin_amdgcn_update_dpp(0.0f, send, 0x141, 0xF, 0xF, false); break;
+      case 0xB1: got = __builtin_amdgcn_update_dpp(0.0f, send, 0xB1, 0xF, 0xF, false); break;
+      case 0x4E: got = __builtin_amdgcn_update_dpp(0.0f, send, 0x4E, 0xF, 0xF, false); break;
+      default: got = __builtin_amdgcn_update_dpp(0.0f, send, 0x128, 0xF, 0xF, false); break;
+    }
+    v[j] = keep + got;
+  }
+}
+
+__device__ __forceinline__ float cross_rows(float x) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = __uint_as_float(a[0]) + __uint_as_float(a[1]);          // rows r and r ^ 1
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);       // halves
+}
+
+// User whose sum lane `lane` holds after wave_sum_scatter<KP>, and whether
+// the lane is the one that stores it (one lane per user, all below 16).
+template <int KP>
+__device__ __forceinline__ int scatter_user(int lane) {
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  if constexpr (KP == 16) return 8 * b2 + 4 * b0 + 2 * b1 + b3;
+  else if constexpr (KP == 8) return 4 * b2 + 2 * b0 + b1;
+  else return 2 * b2 + b0;
+}
+template <int KP>
+__device__ __forceinline__ bool scatter_writer(int lane) {
+  if constexpr (KP == 16) return lane < 16;
+  else if constexpr (KP == 8) return lane < 8;
+  else return lane < 8 && (lane & 2) == 0;
+}
+
+template <int KP>
+__device__ __forceinline__ float wave_sum_scatter(float* v, int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+  scatter_level<KP>(v, b2, 0x141);
+  scatter_level<KP / 2>(v, b0, 0xB1);
+  float x;
+  if constexpr (KP == 4) {
+    x = v[0];
+    x += __builtin_amdgcn_update_dpp(0.0f, x, 0x4E, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0.0f, x, 0x128, 0xF, 0xF, false);
+  } else if constexpr (KP == 8) {
+    scatter_level<2>(v, b1, 0x4E);
+    x = v[0];
+    x += __builtin_amdgcn_update_dpp(0.0f, x, 0x128, 0xF, 0xF, false);
+  } else {
+    scatter_level<4>(v, b1, 0x4E);
+    scatter_level<2>(v, b3, 0x128);
+    x = v[0];
+  }
+  return cross_rows(x);
 }
 
 __device__ __forceinline__ float soft_threshold(float x, float eps) {
@@ -74,12 +131,12 @@ struct Lds {
   float* e;      // [W][KP]  running predictions f(r_j)
   float* c;      // [2W][CS] mu q_j beta_jk of the current step (rows doubled)
   float* bwin;   // [W][KP]  training symbols b_j of the window members
-  float* nrm;    // [W]      ||r_j||^2
+  float* ikjj;   // [W]      1 / kappa(r_j, r_j) (0 where kappa(r_j, r_j) <= 0)
   float* rwin;   // [2R][M2P] window members' vectors and r_{n+1} (rows doubled)
-  float* part;   // [kWaves][KP] per-wave partial sums of f_n(r_n)
+  float* part;   // [KP][kWaves] per-wave partial sums of f_n(r_n)
   float* aev;    // [KP]     coefficients of the evicted entry
   float* omega;  // [W]      position weights
-  float* qden;   // [W+1]    prefix sums of omega
+  float* qs;     // [W+1]    mu / (omega_0 + .. + omega_{L-1}) for |J_n| = L
   float* alds;   // [KP][cap] Gaussian coefficients, k-major (model-buffer path with SLOTS == 0)
 };
 
@@ -101,12 +158,12 @@ __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
   s.e = p; p += W * KP;
   s.c = p; p += 2 * W * CS;
   s.bwin = p; p += W * KP;
-  s.nrm = p; p += W;
+  s.ikjj = p; p += W;
   s.rwin = p; p += 2 * R * M2P;
   s.part = p; p += kWaves * KP;
   s.aev = p; p += KP;
   s.omega = p; p += W;
-  s.qden = p; p += W + 1;
+  s.qs = p; p += W + 1;
   s.alds = p;
   return s;
 }
@@ -208,12 +265,22 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     s.bwin[i] = 0.0f;
   }
   for (int i = tid; i < 2 * W * CS; i += kThreads) s.c[i] = 0.0f;
-  if (tid < W) s.omega[tid] = cm.omega[tid];
-  if (tid == 0) {
-    float acc = 0.0f;
-    s.qden[0] = 0.0f;
-    for (int p = 0; p < W; ++p) { acc += cm.omega[p]; s.qden[p + 1] = acc; }
+  // Position weights and the scale table qs[L] = mu / (omega_0 + .. +
+  // omega_{L-1}), thread p for L = p + 1.  The weights are read at constant
+  // indices (straight from the kernel arguments, no private copy); adding
+  // the zeros past p leaves the left-to-right prefix sum unchanged.
+  if (tid < W) {
+    float acc = 0.0f, om = 0.0f;
+#pragma unroll
+    for (int i = 0; i < APSM_MAX_WINDOW; ++i) {
+      const float o = cm.omega[i];
+      acc += i <= tid ? o : 0.0f;
+      om = i == tid ? o : om;
+    }
+    s.omega[tid] = om;
+    s.qs[tid + 1] = cm.mu / acc;
   }
+  if (tid == 0) s.qs[0] = 0.0f;
 
   // Linear coefficients w = wL v, v[k][m] held as matrix-core accumulators:
   // wave t < M2P/16 holds the 16 x 16 tile of components 16 t .. 16 t + 15
@@ -288,7 +355,10 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     const int L = n + 1 < W ? n + 1 : W;    // |J_n|
     const int evlo = n - cap + 1;           // oldest entry in the dictionary after the append
     if (tid < KP) s.bwin[nw * KP + tid] = bv;
-    if (tid == 0) s.nrm[nw] = nn;
+    if (tid == 0) {
+      const float kjj = fmaf(cm.wl, nn, cm.wg);
+      s.ikjj[nw] = kjj > 0.0f ? 1.0f / kjj : 0.0f;
+    }
 
     float part[KP];
 #pragma unroll
@@ -340,7 +410,8 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       // of each loaded before any is used, so that up to 64 loads are in
       // flight at once (the dictionary is component-major: lanes read
       // consecutive slots, coalesced).
-      constexpr int SB = M2P >= 64 ? 1 : 64 / M2P;
+      constexpr int SB0 = M2P >= 64 ? 1 : 64 / M2P;
+      constexpr int SB = KP == 16 && SB0 > 2 ? 2 : SB0;   // 16 users: bounded by their coefficient registers
       constexpr int MB = M2P >= 64 ? 64 : M2P;
       const int nslot = (n + 1 < cap ? n + 1 : cap);        // slots in use after the append
       if (tid == (sn & (kThreads - 1))) {                   // append (and evict)
@@ -421,46 +492,50 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         }
       }
     }
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const float v = wave_sum_to_last(part[k]);
-      if (lane == 63) s.part[wave * KP + k] = v;
+    {
+      const float v = wave_sum_scatter<KP>(part, lane);
+      if (scatter_writer<KP>(lane)) s.part[scatter_user<KP>(lane) * kWaves + wave] = v;
     }
     __syncthreads();
 
     // ------------------------------------------------------------ phase C
-    const float qscale = cm.mu / s.qden[L];
+    // Every operand is loaded before the first use (one LDS round trip).
+    const float qscale = s.qs[L];
     for (int t = tid; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
       const int jw = ring_sub(nw, p, W);
-      float c = 0.0f;
-      if (k < K) {
-        float e;
-        if (p == 0) {
-          e = 0.0f;
+      const int slot = ring_sub(sn, p, cap);    // dictionary slot of member n - p
+      float pw[kWaves];
 #pragma unroll
-          for (int w = 0; w < kWaves; ++w) e += s.part[w * KP + k];
-        } else {
-          e = s.e[jw * KP + k];
-          if (evicting) e -= s.aev[k] * s.evkr[jw * EVS + (p - 1)];
-        }
+      for (int w = 0; w < kWaves; ++w) pw[w] = s.part[k * kWaves + w];
+      const float eold = s.e[jw * KP + k];
+      const float ev = s.evkr[jw * EVS + (p > 0 ? p - 1 : 0)];
+      const float aev = s.aev[k];
+      const float bw = s.bwin[jw * KP + k];
+      const float ik = s.ikjj[jw];
+      const float om = s.omega[p];
+      float aold = 0.0f;
+      if constexpr (SLOTS == 0) aold = s.alds[k * cap + slot];
+      if constexpr (SLOTS < 0) aold = alpha[(size_t)slot * K + (k < K ? k : 0)];
+
+      // new member: the reduced partial sums; older members: the running
+      // value less the evicted entry's Gaussian term (selects, no branch)
+      float esum = 0.0f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) esum += pw[w];
+      const float eupd = evicting ? eold - aev * ev : eold;
+      const float e = p == 0 ? esum : eupd;
+      const float x = e - bw;
+      const float beta = -soft_threshold(x, cm.eps) * ik;
+      const float c = k < K ? qscale * om * beta : 0.0f;
+      if (k < K) {
         s.e[jw * KP + k] = e;
-        const float x = e - s.bwin[jw * KP + k];
         if (!isfinite(x)) flags |= 1;
-        const float kjj = fmaf(cm.wl, s.nrm[jw], cm.wg);
-        const float beta = kjj > 0.0f ? -soft_threshold(x, cm.eps) / kjj : 0.0f;
-        c = qscale * s.omega[p] * beta;
-        if constexpr (SLOTS <= 0) {
-          // Gaussian coefficient of member n - p (its dictionary slot), one
-          // (member, user) pair per thread; the barrier below orders it
-          // before every later read.
-          const int slot = ring_sub(sn, p, cap);
-          if constexpr (SLOTS == 0) {
-            s.alds[k * cap + slot] = fmaf(c, cm.wg, s.alds[k * cap + slot]);
-          } else {
-            alpha[(size_t)slot * K + k] = fmaf(c, cm.wg, alpha[(size_t)slot * K + k]);
-          }
-        }
+        // Gaussian coefficient of member n - p (model-buffer paths), one
+        // (member, user) pair per thread; the barrier below orders it
+        // before every later read.
+        if constexpr (SLOTS == 0) s.alds[k * cap + slot] = fmaf(c, cm.wg, aold);
+        if constexpr (SLOTS < 0) alpha[(size_t)slot * K + k] = fmaf(c, cm.wg, aold);
       }
       s.c[jw * CS + k] = c;
       s.c[(jw + W) * CS + k] = c;
