@@ -23,8 +23,11 @@ namespace {
 #define APSM_F16_VARIANTS(X) \
   APSM_F16_VARIANTS_M(X, 0, 16) APSM_F16_VARIANTS_M(X, 8, 32) APSM_F16_VARIANTS_M(X, 16, 64)
 
-constexpr int kBatchLds = tile_lds_bytes<64, 8>();   // the largest specialisation
-static_assert(tile_lds_bytes<64, 7>() <= kBatchLds && tile_lds_bytes<32, 8>() <= kBatchLds, "LDS bound");
+// LDS of the largest specialisation (the 2M <= 32 ones stage 128 entries)
+constexpr int kBatchLds = tile_lds_bytes<32, 8>() > tile_lds_bytes<64, 8>() ? tile_lds_bytes<32, 8>()
+                                                                             : tile_lds_bytes<64, 8>();
+static_assert(tile_lds_bytes<64, 7>() <= kBatchLds && tile_lds_bytes<32, 7>() <= kBatchLds &&
+                  tile_lds_bytes<16, 8>() <= kBatchLds, "LDS bound");
 
 // Values every lane holds alike, moved to scalar registers so that the
 // compiler treats the control flow that depends on them (the item loop, the
@@ -66,7 +69,7 @@ __device__ __forceinline__ void run_item(const DetJob* jobs, const int2* items, 
   const DetJob d = load_job(jobs + jx);
   switch (d.variant) {
 #define APSM_F16_CASE(id, M2P, K) \
-  case id: detect_f16_tile<M2P, K>(d, d.packed, tile, lds, werr); break;
+  case id: detect_f16_tile<M2P, K, false>(d, d.packed, tile, lds, werr); break;
     APSM_F16_VARIANTS(APSM_F16_CASE)
 #undef APSM_F16_CASE
     default: break;

@@ -11,16 +11,22 @@
 //
 // Both operands are scaled by powers of two only (so the splits are exact
 // re-scalings): the dictionary by 2^e_d, fixed when the model is packed, and
-// each sample row by its own 2^e_x, so that the largest component lands in
-// [2^12, 2^13) and the lo parts stay clear of FP16 subnormals.  With
+// the 16 samples of a wave by a common 2^e_x, so that their largest
+// component lands in [2^12, 2^13) and the lo parts stay clear of FP16
+// subnormals (for any sample within 2^15 of the largest in its wave; below
+// that the lo parts lose bits only far under the products' rounding).  With
 // acc = 2^(e_x+e_d) (x.d - ||x||^2 / 2) from the MFMA (the row term enters as
 // its C operand), the exponent argument is
-//   log2(kappa_G) = fma(acc, 2c 2^-(e_x+e_d), -c ||d||^2),  c = log2(e) / (2 sigma^2).
+//   log2(kappa_G) = fma(acc, 2c 2^-(e_x+e_d), -c ||d||^2),  c = log2(e) / (2 sigma^2),
+// with the multiplier the same for the whole wave (a scalar register).
 //
 // Layout: samples are the MFMA rows (A operand), held in registers for the
 // whole dictionary sweep; dictionary entries are the columns (B operand),
-// streamed through LDS in chunks of 64 from the packed model with a plain
-// 16-byte copy that is prefetched one chunk ahead.  Accumulator element r of
+// streamed through LDS in chunks of 128 (2M <= 32) or 64 entries from the
+// packed model with a plain 16-byte copy that is prefetched one chunk ahead.
+// For 2M <= 32, within a chunk the products of the next 32-entry tile are
+// issued before the exp2 and coefficient work of the current one, so that
+// the matrix cores run them while the VALU works.  Accumulator element r of
 // lane l is sample row 8(r/4) + 4(l/32) + r%4 against dictionary column l%32,
 // so each lane needs the K coefficients of one dictionary entry per tile and
 // keeps 16 x K partial outputs; a reduce-scatter across the 32 columns at the
@@ -38,11 +44,16 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kChunk = 64;                 // dictionary entries per LDS stage
+constexpr int kPad = 128;                  // packed-model rows are padded to a multiple of this
 constexpr int kHeader = 64;                // packed-model header bytes
 
 template <int M2P, int K>
 struct Geo {
+  static constexpr int CH = M2P <= 32 ? 128 : 64;  // dictionary entries per LDS stage
+  static constexpr int CT = CH / 32;               // 32-entry tiles per stage
+  // products of the next tile issued ahead of the current tile's VALU work
+  // (a second accumulator set: 2M = 64 has no registers to spare for it)
+  static constexpr bool PIPE = M2P <= 32;
   static constexpr int NB = M2P / 16;              // 16-deep blocks per segment
   static constexpr int NSTEP = 3 * NB;             // [hi|lo|hi] x [hi|hi|lo]
   static constexpr int BSTR = 2 * M2P + 8;         // packed row: d_hi | d_lo | pad (halves)
@@ -50,8 +61,8 @@ struct Geo {
   static constexpr int K4 = (K + 3) / 4 * 4;
   static constexpr int CSTR = K4 + 4;              // per-entry floats: K4 coefficients, ||d||^2, pad
   static constexpr int KE = K + (K & 1);           // even user count for the reduce-scatter
-  static constexpr int A_BYTES = kChunk * ROW_B;
-  static constexpr int C_BYTES = kChunk * CSTR * 4;
+  static constexpr int A_BYTES = CH * ROW_B;
+  static constexpr int C_BYTES = CH * CSTR * 4;
   static constexpr int STAGE_BYTES = A_BYTES + C_BYTES;
 };
 
@@ -59,14 +70,20 @@ struct Geo {
 // 64.  The packed layout, its size and the kernel dispatch all use this one
 // value (a 2M of 40 runs, and is packed, with the 64-wide layout).
 __host__ __device__ inline int m2p_f16(int m2) { return m2 <= 16 ? 16 : m2 <= 32 ? 32 : 64; }
-__host__ __device__ inline int cap64_of(int cap) { return (cap + kChunk - 1) / kChunk * kChunk; }
+__host__ __device__ inline int cap_pad(int cap) { return (cap + kPad - 1) / kPad * kPad; }
 
 inline bool supported(int M2, int K) { return M2 <= 64 && K <= 8; }
 
 // Bytes of the packed model for a supported shape.
 inline size_t packed_bytes(int M2, int K, int cap) {
   const int M2P = m2p_f16(M2), K4 = (K + 3) / 4 * 4;
-  return kHeader + (size_t)cap64_of(cap) * ((2 * M2P + 8) * 2 + (K4 + 4) * 4);
+  return kHeader + (size_t)cap_pad(cap) * ((2 * M2P + 8) * 2 + (K4 + 4) * 4);
+}
+
+// A float every lane holds alike, in a scalar register (the readfirstlane
+// builtin takes and returns int: the bits are moved, not the value converted).
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
 __device__ __forceinline__ void split_f16(float v, _Float16& hi, _Float16& lo) {
@@ -90,55 +107,51 @@ hipError_t launch_detect_f16_m16(const DetectArgs& a, const unsigned char* packe
 hipError_t launch_detect_f16_m32(const DetectArgs& a, const unsigned char* packed, hipStream_t stream);
 hipError_t launch_detect_f16_m64(const DetectArgs& a, const unsigned char* packed, hipStream_t stream);
 
-// Next chunk of the packed model, held in registers while the current chunk
-// is being computed.
+typedef __attribute__((address_space(1))) void global_void;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Copy of one stage of the packed model (rows row0 .. row0 + CH - 1: their
+// halves, then their coefficients) straight from global memory into LDS with
+// gfx950's global_load_lds_dwordx4: each lane moves 16 bytes, so one
+// instruction of a wave fills a contiguous KiB of the stage.  Asynchronous:
+// stage_wait() before the barrier that publishes the stage.
 template <int M2P, int K>
-struct Prefetch {
+__device__ __forceinline__ void stage_async(const unsigned char* packed, int capp, int row0,
+                                            unsigned char* st, int wave, int lane) {
   using G = Geo<M2P, K>;
-  static constexpr int NA = (G::A_BYTES / 16 + kThreads - 1) / kThreads;
-  static constexpr int NC = (G::C_BYTES / 16 + kThreads - 1) / kThreads;
-  floatx4 ra[NA], rc[NC];
-  __device__ __forceinline__ void load(const unsigned char* packed, int cap64, int row0) {
-    const floatx4* srcA = reinterpret_cast<const floatx4*>(packed + kHeader + (size_t)row0 * G::ROW_B);
-    const floatx4* srcC = reinterpret_cast<const floatx4*>(packed + kHeader + (size_t)cap64 * G::ROW_B +
-                                                           (size_t)row0 * G::CSTR * 4);
+  static_assert(G::A_BYTES % 1024 == 0 && G::C_BYTES % 1024 == 0, "stage sections in whole KiB");
+  constexpr int NA = G::A_BYTES / 1024, NC = G::C_BYTES / 1024;
+  const unsigned char* srcA = packed + kHeader + (size_t)row0 * G::ROW_B;
+  const unsigned char* srcC = packed + kHeader + (size_t)capp * G::ROW_B + (size_t)row0 * G::CSTR * 4;
 #pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int e = threadIdx.x + u * kThreads;
-      if (e < G::A_BYTES / 16) ra[u] = srcA[e];
-    }
-#pragma unroll
-    for (int u = 0; u < NC; ++u) {
-      const int e = threadIdx.x + u * kThreads;
-      if (e < G::C_BYTES / 16) rc[u] = srcC[e];
+  for (int u = 0; u < (NA + NC + kWaves - 1) / kWaves; ++u) {
+    const int blk = u * kWaves + wave;       // wave-uniform
+    if (blk < NA) {
+      __builtin_amdgcn_global_load_lds((global_void*)(srcA + blk * 1024 + lane * 16),
+                                       (lds_void*)(st + blk * 1024), 16, 0, 0);
+    } else if (blk < NA + NC) {
+      __builtin_amdgcn_global_load_lds((global_void*)(srcC + (blk - NA) * 1024 + lane * 16),
+                                       (lds_void*)(st + G::A_BYTES + (blk - NA) * 1024), 16, 0, 0);
     }
   }
-  __device__ __forceinline__ void store(unsigned char* st) const {
-    floatx4* dA = reinterpret_cast<floatx4*>(st);
-    floatx4* dC = reinterpret_cast<floatx4*>(st + G::A_BYTES);
-#pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int e = threadIdx.x + u * kThreads;
-      if (e < G::A_BYTES / 16) dA[e] = ra[u];
-    }
-#pragma unroll
-    for (int u = 0; u < NC; ++u) {
-      const int e = threadIdx.x + u * kThreads;
-      if (e < G::C_BYTES / 16) dC[e] = rc[u];
-    }
-  }
-};
+}
+
+// Wait for this wave's outstanding global loads (stage copies included):
+// s_waitcnt vmcnt(0) with the other counters left open.
+__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // LDS bytes of one tile: two dictionary stages and the linear coefficients.
 template <int M2P, int K>
 constexpr int tile_lds_bytes() { return 2 * Geo<M2P, K>::STAGE_BYTES + K * M2P * 4; }
 
 // Detection of one tile of kWaves * 16 received vectors (vectors tile * 64 ..
-// tile * 64 + 63) by the whole workgroup.  A is DetectArgs or DetJob (the same
+// tile * 64 + 63) by the whole workgroup.  ALLOW_PIPE: the caller has the
+// registers for the one-tile-ahead products (a function holding every
+// specialisation does not).  A is DetectArgs or DetJob (the same
 // field names); lds holds tile_lds_bytes<M2P, K>() bytes (16-byte aligned),
 // werr 8 counters.  A workgroup may run tiles back to back on the same LDS
 // when a barrier separates them.
-template <int M2P, int K, class A>
+template <int M2P, int K, bool ALLOW_PIPE, class A>
 __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char* packed, int tile,
                                                 unsigned char* lds, unsigned int* werr) {
   using G = Geo<M2P, K>;
@@ -146,10 +159,10 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
   float* wl = reinterpret_cast<float*>(lds + 2 * G::STAGE_BYTES);
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int j = lane & 31, h = lane >> 5;
   const int M2 = a.M2, M = a.M2 / 2;
-  const int cap64 = cap64_of(a.cap);
+  const int capp = cap_pad(a.cap);
   // Entries in use and the dictionary exponent are the same for every lane;
   // in scalar registers they keep the chunk loop (which holds barriers)
   // uniform control flow.
@@ -186,8 +199,9 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
       mx = fmaxf(mx, fabsf(t));
     }
   nrm += __shfl_xor(nrm, 32);
-  mx = fmaxf(mx, __shfl_xor(mx, 32));
-  const int e_x = scale_exp(mx);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+  const int e_x = __builtin_amdgcn_readfirstlane(scale_exp(mx));
   const float xsc = ldexpf(1.0f, e_x);
   half8 afr[NSTEP];
 #pragma unroll
@@ -201,15 +215,10 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
       afr[2 * NB + b][v] = hi;
     }
   const float my_cinit = ldexpf(-0.5f * nrm, e_x + e_d);
-  const float my_desc = ldexpf(2.0f * a.c2, -(e_x + e_d));
+  const float desc = uniform_f(ldexpf(2.0f * a.c2, -(e_x + e_d)));
   floatx16 cinit;
-  float desc[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int src = 8 * (r / 4) + 4 * h + (r % 4);
-    cinit[r] = __shfl(my_cinit, src);
-    desc[r] = __shfl(my_desc, src);
-  }
+  for (int r = 0; r < 16; ++r) cinit[r] = __shfl(my_cinit, 8 * (r / 4) + 4 * h + (r % 4));
 
   float acc_k[16][KE];
 #pragma unroll
@@ -218,45 +227,62 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
     for (int k = 0; k < KE; ++k) acc_k[r][k] = 0.0f;
 
   // ---- dictionary sweep
-  const int nchunks = (D + kChunk - 1) / kChunk;
-  Prefetch<M2P, K> pf;
-  if (nchunks > 0) {
-    pf.load(packed, cap64, 0);
-    pf.store(lds);
-  }
+  constexpr int CH = G::CH, CT = G::CT;
+  const float mc2 = uniform_f(-a.c2);
+  // products of tile ct of a stage: acc = cinit + x.d (split FP16)
+  auto products = [&](const _Float16* dh, int ct) {
+    const _Float16* brow = dh + (ct * 32 + j) * G::BSTR + 8 * h;
+    floatx16 acc = cinit;
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+      // B steps: d_hi blocks (paired with x_hi, then x_lo), then d_lo blocks
+      const int off = s < NB ? 16 * s : (s < 2 * NB ? 16 * (s - NB) : M2P + 16 * (s - 2 * NB));
+      const half8 bv = *reinterpret_cast<const half8*>(brow + off);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(afr[s], bv, acc, 0, 0, 0);
+    }
+    return acc;
+  };
+  // exp2 and the coefficient FMAs of tile ct
+  auto expand = [&](const float* co, int ct, const floatx16& acc) {
+    float cr[CSTR];
+    const float* cp = co + (ct * 32 + j) * CSTR;
+#pragma unroll
+    for (int q = 0; q < CSTR; q += 4) {
+      const floatx4 v4 = *reinterpret_cast<const floatx4*>(cp + q);
+      cr[q] = v4[0]; cr[q + 1] = v4[1]; cr[q + 2] = v4[2]; cr[q + 3] = v4[3];
+    }
+    const float coln = mc2 * cr[K4];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float kap = __builtin_amdgcn_exp2f(fmaf(acc[r], desc, coln));
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc_k[r][k] = fmaf(cr[k], kap, acc_k[r][k]);
+    }
+  };
+  const int nchunks = (D + CH - 1) / CH;
+  if (nchunks > 0) stage_async<M2P, K>(packed, capp, 0, lds, wave, lane);
+  stage_wait();
   __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
-    if (c + 1 < nchunks) pf.load(packed, cap64, (c + 1) * kChunk);
+    // the next stage was last read in chunk c - 1, which every wave has left
+    if (c + 1 < nchunks) stage_async<M2P, K>(packed, capp, (c + 1) * CH, lds + ((c + 1) & 1) * G::STAGE_BYTES, wave, lane);
     const unsigned char* st = lds + (c & 1) * G::STAGE_BYTES;
     const _Float16* dh = reinterpret_cast<const _Float16*>(st);
     const float* co = reinterpret_cast<const float*>(st + G::A_BYTES);
+    if constexpr (G::PIPE && ALLOW_PIPE) {
+      floatx16 acc = products(dh, 0);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        floatx16 next;
+        if (ct + 1 < CT) next = products(dh, ct + 1);
+        expand(co, ct, acc);
+        if (ct + 1 < CT) acc = next;
+      }
+    } else {
 #pragma unroll 1
-    for (int ct = 0; ct < kChunk / 32; ++ct) {
-      const _Float16* brow = dh + (ct * 32 + j) * G::BSTR + 8 * h;
-      floatx16 acc = cinit;
-#pragma unroll
-      for (int s = 0; s < NSTEP; ++s) {
-        // B steps: d_hi blocks (paired with x_hi, then x_lo), then d_lo blocks
-        const int off = s < NB ? 16 * s : (s < 2 * NB ? 16 * (s - NB) : M2P + 16 * (s - 2 * NB));
-        const half8 bv = *reinterpret_cast<const half8*>(brow + off);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(afr[s], bv, acc, 0, 0, 0);
-      }
-      float cr[CSTR];
-      const float* cp = co + (ct * 32 + j) * CSTR;
-#pragma unroll
-      for (int q = 0; q < CSTR; q += 4) {
-        const floatx4 v4 = *reinterpret_cast<const floatx4*>(cp + q);
-        cr[q] = v4[0]; cr[q + 1] = v4[1]; cr[q + 2] = v4[2]; cr[q + 3] = v4[3];
-      }
-      const float coln = -a.c2 * cr[K4];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float kap = __builtin_amdgcn_exp2f(fmaf(acc[r], desc[r], coln));
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc_k[r][k] = fmaf(cr[k], kap, acc_k[r][k]);
-      }
+      for (int ct = 0; ct < CT; ++ct) expand(co, ct, products(dh, ct));
     }
-    if (c + 1 < nchunks) pf.store(lds + ((c + 1) & 1) * G::STAGE_BYTES);
+    stage_wait();
     __syncthreads();
   }
 
@@ -299,7 +325,8 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
     }
   }
   const int bits = a.modulation >> 1;              // per axis: 1 (QPSK) or 2 (16-QAM)
-  const bool has_err = a.err != nullptr;
+  // uniform by construction (it guards a barrier)
+  const bool has_err = __builtin_amdgcn_readfirstlane((int)(a.err != nullptr)) != 0;
 #pragma unroll
   for (int u = 0; u < KE / 2; ++u) {
     const int k = k0 + u;
@@ -333,7 +360,7 @@ template <int M2P, int K>
 __global__ __launch_bounds__(kThreads, 2) void detect_f16_kernel(DetectArgs a, const unsigned char* packed) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[tile_lds_bytes<M2P, K>()];
   __shared__ unsigned int werr[8];
-  detect_f16_tile<M2P, K>(a, packed, blockIdx.x, lds, werr);
+  detect_f16_tile<M2P, K, true>(a, packed, blockIdx.x, lds, werr);
 }
 
 }  // namespace f16

@@ -35,13 +35,13 @@ __global__ __launch_bounds__(1024) void dict_scale_kernel(const float* dict, con
   dict_scale_body(dict, state, cap, M2, header, red);
 }
 
-// Row i of the packed model (one thread per row; rows up to cap64).
+// Row i of the packed model (one thread per row; rows up to cap_pad(cap)).
 template <int M2P, int K>
 __device__ __forceinline__ void pack_row(const float* dict, const float* alpha, const int32_t* state, int cap,
                                          int M2, unsigned char* out, int i) {
   using G = Geo<M2P, K>;
-  const int cap64 = cap64_of(cap);
-  if (i >= cap64) return;
+  const int capp = cap_pad(cap);
+  if (i >= capp) return;
   int D = state[0];
   D = D < 0 ? 0 : (D > cap ? cap : D);
   const bool valid = i < D;
@@ -58,7 +58,7 @@ __device__ __forceinline__ void pack_row(const float* dict, const float* alpha, 
     row[M2P + m] = lo;
   }
   for (int v = 0; v < 8; ++v) row[2 * M2P + v] = (_Float16)0.0f;
-  float* co = reinterpret_cast<float*>(out + kHeader + (size_t)cap64 * G::ROW_B) + (size_t)i * G::CSTR;
+  float* co = reinterpret_cast<float*>(out + kHeader + (size_t)capp * G::ROW_B) + (size_t)i * G::CSTR;
   for (int k = 0; k < G::K4; ++k) co[k] = (valid && k < K) ? alpha[(size_t)i * K + k] : 0.0f;
   co[G::K4] = n;
   co[G::K4 + 1] = co[G::K4 + 2] = co[G::K4 + 3] = 0.0f;
@@ -99,8 +99,8 @@ hipError_t pack_mk(const float* dict, const float* alpha, const int32_t* state, 
                    unsigned char* packed, hipStream_t stream) {
   hipLaunchKernelGGL(dict_scale_kernel, dim3(1), dim3(1024), 0, stream, dict, state, cap, M2,
                      reinterpret_cast<int*>(packed));
-  const int cap64 = cap64_of(cap);
-  hipLaunchKernelGGL((pack_kernel<M2P, K>), dim3((cap64 + 255) / 256), dim3(256), 0, stream, dict, alpha,
+  const int capp = cap_pad(cap);
+  hipLaunchKernelGGL((pack_kernel<M2P, K>), dim3((capp + 255) / 256), dim3(256), 0, stream, dict, alpha,
                      state, cap, M2, packed);
   return hipGetLastError();
 }
@@ -128,7 +128,7 @@ hipError_t pack_m(const float* dict, const float* alpha, const int32_t* state, i
 hipError_t launch_pack_batch(const PackJob* jobs, int n, int max_cap, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(dict_scale_batch_kernel, dim3(n), dim3(1024), 0, stream, jobs);
-  const int blocks = (cap64_of(max_cap) + 255) / 256;
+  const int blocks = (cap_pad(max_cap) + 255) / 256;
   hipLaunchKernelGGL(pack_batch_kernel, dim3(blocks, n), dim3(256), 0, stream, jobs);
   return hipGetLastError();
 }

@@ -125,7 +125,7 @@ def test_packed_bytes():
     assert L.apsm_model_packed_bytes(32, 6, 1000) == 64 + 1024 * (72 * 2 + 12 * 4)
     assert L.apsm_model_packed_bytes(128, 16, 1000) == 0      # detected without a packed form
     # 2M = 40 runs with the 64-wide layout: rows of 2*64+8 halves, K4 + 4 floats each
-    assert L.apsm_model_packed_bytes(40, 2, 40) == 64 + 64 * ((2 * 64 + 8) * 2 + (4 + 4) * 4)
+    assert L.apsm_model_packed_bytes(40, 2, 40) == 64 + 128 * ((2 * 64 + 8) * 2 + (4 + 4) * 4)
     for m2 in range(34, 65, 2):
         assert L.apsm_model_packed_bytes(m2, 5, 300) == L.apsm_model_packed_bytes(64, 5, 300), m2
     for m2 in range(18, 33, 2):
