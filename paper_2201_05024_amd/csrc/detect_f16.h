@@ -140,9 +140,12 @@ __device__ __forceinline__ void stage_async(const unsigned char* packed, int cap
 // s_waitcnt vmcnt(0) with the other counters left open.
 __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// LDS bytes of one tile: two dictionary stages and the linear coefficients.
+// LDS bytes of one tile: two dictionary stages, the linear coefficients and
+// each wave's linear terms (32 rows x KE users).
 template <int M2P, int K>
-constexpr int tile_lds_bytes() { return 2 * Geo<M2P, K>::STAGE_BYTES + K * M2P * 4; }
+constexpr int tile_lds_bytes() {
+  return 2 * Geo<M2P, K>::STAGE_BYTES + K * M2P * 4 + kWaves * 32 * Geo<M2P, K>::KE * 4;
+}
 
 // Detection of one tile of kWaves * 16 received vectors (vectors tile * 64 ..
 // tile * 64 + 63) by the whole workgroup.  ALLOW_PIPE: the caller has the
@@ -160,6 +163,7 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  float* lin_w = wl + K * M2P + wave * 32 * KE;     // this wave's linear terms: [32][KE]
   const int j = lane & 31, h = lane >> 5;
   const int M2 = a.M2, M = a.M2 / 2;
   const int capp = cap_pad(a.cap);
@@ -263,6 +267,34 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
   if (nchunks > 0) stage_async<M2P, K>(packed, capp, 0, lds, wave, lane);
   stage_wait();
   __syncthreads();
+
+  // ---- linear part w_k . r of this lane's A row (half of its components
+  // here, the other half in lane ^ 32: summed by the row-half swap), kept
+  // in this wave's LDS rows for the lanes that finish the row.  Only this
+  // wave reads them, after its own writes (LDS operations of a wave are
+  // processed in order).
+  {
+    float plin[KE];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) plin[k] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+#pragma unroll
+        for (int k = 0; k < K; ++k) plin[k] = fmaf(wl[k * M2P + 16 * b + 8 * h + v], xv[8 * b + v], plin[k]);
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(plin[k]), __float_as_uint(plin[k]),
+                                                        false, false);
+      plin[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    }
+    if (h == 0) {
+#pragma unroll
+      for (int k = 0; k < KE; ++k) lin_w[j * KE + k] = plin[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
   for (int c = 0; c < nchunks; ++c) {
     // the next stage was last read in chunk c - 1, which every wave has left
     if (c + 1 < nchunks) stage_async<M2P, K>(packed, capp, (c + 1) * CH, lds + ((c + 1) & 1) * G::STAGE_BYTES, wave, lane);
@@ -292,38 +324,44 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
   for (int r = 0; r < 16; ++r)
 #pragma unroll
     for (int k = 0; k < KE; ++k) v[r * KE + k] = acc_k[r][k];
+  // (The DPP lambdas state their float return type: deduced, the builtin's
+  // result would be taken as an int.)
+  // Five exchange levels between lanes of the same half whose column
+  // indices differ by 16 (gfx950 row swap: both halves of a pair move at
+  // once), 8 (row_ror:8), 7 (row_half_mirror), 1 and 2 (quad_perm).  Each
+  // level keeps half of the values, chosen by one bit of the column index
+  // (4, 3, 2, 0, 1 in that order), and adds the partner's copy of them.
+  constexpr int N = 16 * KE;
 #pragma unroll
-  for (int t = 0; t < 5; ++t) {
-    const int half = (16 * KE) >> (t + 1);
-    const int mask = 16 >> t;
-    const bool upper = (lane & mask) != 0;
+  for (int i = 0; i < N / 2; ++i) {
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[N / 2 + i]),
+                                                      false, false);
+    v[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+  }
+  auto level = [&](int half, bool upper, auto dpp) {
 #pragma unroll
     for (int i = 0; i < half; ++i) {
       const float send = upper ? v[i] : v[half + i];
       const float keep = upper ? v[half + i] : v[i];
-      v[i] = keep + __shfl_xor(send, mask);
+      v[i] = keep + dpp(send);
     }
-  }
-  // Lane (j, h) now holds accumulator row r = j/2 (sample row
-  // 8(r/4) + 4h + r%4) for users k0 .. k0 + KE/2 - 1, k0 = (j%2) KE/2.
-  const int r = j >> 1;
+  };
+  level(N / 4, (lane & 8) != 0, [](float x) -> float { return __builtin_amdgcn_update_dpp(0.0f, x, 0x128, 0xF, 0xF, false); });
+  level(N / 8, (lane & 4) != 0, [](float x) -> float { return __builtin_amdgcn_update_dpp(0.0f, x, 0x141, 0xF, 0xF, false); });
+  level(N / 16, (lane & 1) != 0, [](float x) -> float { return __builtin_amdgcn_update_dpp(0.0f, x, 0xB1, 0xF, 0xF, false); });
+  level(N / 32, (lane & 2) != 0, [](float x) -> float { return __builtin_amdgcn_update_dpp(0.0f, x, 0x4E, 0xF, 0xF, false); });
+  // Lane (j, h) now holds accumulator row r = jj/2 (sample row
+  // 8(r/4) + 4h + r%4) for users k0 .. k0 + KE/2 - 1, k0 = (jj%2) KE/2,
+  // where jj is j with its bits 0 and 1 exchanged (the order of the levels).
+  const int jj = (j & ~3) | ((j & 1) << 1) | ((j >> 1) & 1);
+  const int r = jj >> 1;
   const int rho = 8 * (r >> 2) + 4 * h + (r & 3);
   const int smp = s0 + (rho >> 1), part = rho & 1;
   const bool valid = smp < a.S;
-  const int k0 = (j & 1) * (KE / 2);
-  const float* xr = a.rx + (size_t)(valid ? smp : 0) * M2;
+  const int k0 = (jj & 1) * (KE / 2);
   float lin[KE / 2];
 #pragma unroll
-  for (int u = 0; u < KE / 2; ++u) lin[u] = 0.0f;
-  for (int m = 0; m < M2; ++m) {
-    const int src = part == 0 ? m : (m < M ? m + M : m - M);
-    const float xvm = (part == 1 && m >= M) ? -xr[src] : xr[src];
-#pragma unroll
-    for (int u = 0; u < KE / 2; ++u) {
-      const int k = k0 + u < K ? k0 + u : K - 1;
-      lin[u] = fmaf(wl[k * M2P + m], xvm, lin[u]);
-    }
-  }
+  for (int u = 0; u < KE / 2; ++u) lin[u] = lin_w[rho * KE + k0 + u];
   const int bits = a.modulation >> 1;              // per axis: 1 (QPSK) or 2 (16-QAM)
   // uniform by construction (it guards a barrier)
   const bool has_err = __builtin_amdgcn_readfirstlane((int)(a.err != nullptr)) != 0;
@@ -342,7 +380,7 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
         idx = (val >= -th) + (val >= 0.0f) + (val >= th);
       }
       const int gr = idx ^ (idx >> 1);
-      const int other = __shfl_xor(gr, 2);         // the lane holding the other part of this sample
+      const int other = __shfl_xor(gr, 1);         // the lane holding the other part of this sample
       const int label = part == 0 ? ((gr << bits) | other) : ((other << bits) | gr);
       if (part == 0 && valid && kval) {
         if (a.hard) a.hard[(size_t)smp * a.K + k] = (uint8_t)label;
