@@ -217,8 +217,11 @@ typedef struct apsm_batch apsm_batch_t;   /* opaque host object */
 int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* items, int n,
                       apsm_batch_t** out);
 
-/* Bytes of device workspace the batch needs (job tables, the work-item list
- * of detection and two claim counters). */
+/* Bytes of device workspace the batch needs: job tables, the work-item list
+ * of detection, two claim counters and the training kernel rows (for each
+ * detector with dict_cap <= 4096: 2P x (dict_cap + window) floats, the
+ * Gaussian kernel values of every pilot step against the dictionary entries
+ * it sees, computed by one data-parallel launch before training). */
 size_t apsm_batch_workspace_bytes(const apsm_batch_t* batch);
 
 /* Write the batch's tables into `workspace` (DEVICE, at least
@@ -236,8 +239,18 @@ int apsm_batch_bind(apsm_batch_t* batch, void* workspace, size_t bytes, void* st
 int apsm_batch_tune(apsm_batch_t* batch, void* stream);
 
 /* Train every detector of the batch (same results as apsm_train per item)
- * and pack the models; asynchronous on `stream`. */
+ * and pack the models; asynchronous on `stream`.  The same as
+ * apsm_batch_kernel_rows followed by apsm_batch_train_prepared on `stream`. */
 int apsm_batch_train(const apsm_batch_t* batch, void* stream);
+
+/* The two parts of apsm_batch_train, for callers that schedule them on
+ * different streams.  apsm_batch_kernel_rows computes the kernel rows of the
+ * batch's pilots into the workspace (one data-parallel launch over the whole
+ * GPU); apsm_batch_train_prepared trains and packs from them and must be
+ * ordered after that launch (same stream, or an event), with the pilots
+ * unchanged in between.  Calls of one batch must not overlap. */
+int apsm_batch_kernel_rows(const apsm_batch_t* batch, void* stream);
+int apsm_batch_train_prepared(const apsm_batch_t* batch, void* stream);
 
 /* Detect every item's received vectors (same results as apsm_detect per
  * item); asynchronous on `stream`.  Calls of one batch must not overlap

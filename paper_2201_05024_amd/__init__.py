@@ -97,6 +97,10 @@ def library() -> ctypes.CDLL:
         L.apsm_batch_tune.restype = i32
         L.apsm_batch_train.argtypes = [vp, vp]
         L.apsm_batch_train.restype = i32
+        L.apsm_batch_kernel_rows.argtypes = [vp, vp]
+        L.apsm_batch_kernel_rows.restype = i32
+        L.apsm_batch_train_prepared.argtypes = [vp, vp]
+        L.apsm_batch_train_prepared.restype = i32
         L.apsm_batch_detect.argtypes = [vp, vp]
         L.apsm_batch_detect.restype = i32
         L.apsm_batch_destroy.argtypes = [vp]
@@ -353,7 +357,9 @@ class Batch:
         self._h = h
         nbytes = library().apsm_batch_workspace_bytes(h)
         dev = self.items[0].rx_pilot.device
-        self.workspace = torch.zeros(nbytes + 256, dtype=torch.uint8, device=dev)
+        # apsm_batch_bind writes the tables (counters included); the kernel
+        # rows after them are computed on the device, so no clearing is needed
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         off = (-self.workspace.data_ptr()) % 256
         self._ws_ptr = self.workspace.data_ptr() + off
         rc = library().apsm_batch_bind(h, self._ws_ptr, nbytes, _stream_handle(stream))
@@ -370,6 +376,20 @@ class Batch:
         rc = library().apsm_batch_train(self._h, _stream_handle(stream))
         if rc:
             raise APSMError(rc, "apsm_batch_train")
+        return self
+
+    def kernel_rows(self, stream=None) -> "Batch":
+        """First part of train(): the kernel rows of the pilots (whole GPU)."""
+        rc = library().apsm_batch_kernel_rows(self._h, _stream_handle(stream))
+        if rc:
+            raise APSMError(rc, "apsm_batch_kernel_rows")
+        return self
+
+    def train_prepared(self, stream=None) -> "Batch":
+        """Second part of train(), ordered after kernel_rows() by the caller."""
+        rc = library().apsm_batch_train_prepared(self._h, _stream_handle(stream))
+        if rc:
+            raise APSMError(rc, "apsm_batch_train_prepared")
         return self
 
     def detect(self, stream=None) -> "Batch":

@@ -34,6 +34,11 @@ struct TrainJob {
   int P, M2, K, cap;
   float c2;               // log2e / (2 sigma^2)
   int variant;            // kernel specialisation (train_variant), table launches only
+  // Precomputed kernel rows (rows launches only, else null): for step n,
+  // glag[n * cap + l] = kappa_G(r_n, r_{n-l}) (0 for l > n) and
+  // kw[n * W + q] = K(r_n, r_{n-q}) = wL r_n.r_{n-q} + wG kappa_G(r_n, r_{n-q}).
+  float* glag;
+  float* kw;
 };
 
 // Training launch of n_inst detectors of one shape, all by value (kernel
@@ -96,6 +101,21 @@ int train_variant(int M2, int K, int W, int cap);
 size_t train_lds_bytes(int W, int M2, int K, int cap);
 hipError_t launch_train_table(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
                               hipStream_t stream);
+// Training from precomputed kernel rows (every shape up to 2M = 128 whose
+// dictionary fits 8 register slots per thread, cap <= 4096): the rows are
+// written by launch_kernel_rows from the same job table, one workgroup per
+// item (job, n0, l0, 0) covering steps n0 .. n0 + kernel_rows_tile_steps() - 1
+// and lags l0 .. l0 + kernel_rows_tile_lags() - 1 (max_M2: the largest 2M of
+// the jobs), then launch_train_rows trains, workgroup b running jobs[b] with
+// the variant train_rows_variant set.
+int train_rows_variant(int M2, int K, int cap);   // -1 if the shape is not covered
+size_t train_rows_lds_bytes(int W, int M2, int K);
+int kernel_rows_tile_steps();
+int kernel_rows_tile_lags();
+hipError_t launch_kernel_rows(const TrainJob* jobs, const int4* items, int n_items, int max_M2,
+                              const TrainCommon& cm, hipStream_t stream);
+hipError_t launch_train_rows(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
+                             hipStream_t stream);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t stream);
 // Packed model for the split-FP16 detection path: bytes (0 when the shape
 // uses the FP32 path) and the packing launch (no-op for such shapes).

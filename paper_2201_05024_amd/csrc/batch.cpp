@@ -3,8 +3,10 @@
 // and their tuning.
 //
 // Planning: every item becomes one training job (one workgroup, its kernel
-// specialisation picked by train_variant), ordered by estimated cost so the
-// longest trainings start first.  Items whose shape the split-FP16 path
+// specialisation picked by train_rows_variant, else train_variant), ordered
+// by estimated cost so the longest trainings start first.  Jobs of the rows
+// form get their kernel rows (one step per row) in the workspace, written by
+// one data-parallel launch before the training launch.  Items whose shape the split-FP16 path
 // covers (2M <= 64, K <= 8) become packing jobs and detection jobs; their
 // 64-vector tiles form one global work-item list, ordered by the cost of a
 // tile (dictionary size times per-entry work), most expensive first.  Other
@@ -25,13 +27,18 @@ struct apsm_batch {
   apsm::TrainCommon cm{};
   std::vector<apsm::TrainJob> tjobs;
   size_t train_lds = 0;
+  std::vector<apsm::TrainJob> rjobs;          // rows form; glag/kw set at bind
+  std::vector<size_t> rows_off;               // float offset of each rows job's glag (kw follows)
+  std::vector<int4> ritems;                   // (rows job, first step, first lag) per kernel-row tile
+  size_t rows_lds = 0, rows_floats = 0;
+  int rows_max_m2 = 0;
   std::vector<apsm::PackJob> pjobs;
   int pack_max_cap = 0;
   std::vector<apsm::DetJob> djobs;
   std::vector<int2> ditems;
   std::vector<int> plain;            // items detected with their own launch
   std::vector<int> train_plain;      // items trained with their own launch
-  size_t off_t = 0, off_p = 0, off_d = 0, off_i = 0, off_c = 0, bytes = 0;
+  size_t off_t = 0, off_rj = 0, off_ri = 0, off_p = 0, off_d = 0, off_i = 0, off_c = 0, off_rows = 0, bytes = 0;
   unsigned char* ws = nullptr;       // bound workspace (device)
   bool persistent = true;
   int grid = 0;
@@ -103,7 +110,8 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tcost[a] > tcost[c]; });
   for (int i : order) {
     const auto& it = b.items[i];
-    if (!train_in_table(it.model.M2)) {
+    const int rv = train_rows_variant(it.model.M2, it.model.K, it.model.dict_cap);
+    if (rv < 0 && !train_in_table(it.model.M2)) {
       b.train_plain.push_back(i);
       continue;
     }
@@ -119,6 +127,18 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
     j.K = it.model.K;
     j.cap = it.model.dict_cap;
     j.c2 = kLog2e / (2.0f * it.sigma2);
+    if (rv >= 0) {
+      const int q = (int)b.rjobs.size(), T = 2 * it.P;
+      j.variant = rv;
+      b.rjobs.push_back(j);
+      b.rows_off.push_back(b.rows_floats);
+      b.rows_floats += (size_t)T * (j.cap + p->window);
+      b.rows_lds = std::max(b.rows_lds, train_rows_lds_bytes(p->window, j.M2, j.K));
+      b.rows_max_m2 = std::max(b.rows_max_m2, j.M2);
+      for (int n0 = 0; n0 < T; n0 += kernel_rows_tile_steps())
+        for (int l0 = 0; l0 < j.cap; l0 += kernel_rows_tile_lags()) b.ritems.push_back(make_int4(q, n0, l0, 0));
+      continue;
+    }
     j.variant = train_variant(j.M2, j.K, p->window, j.cap);
     b.tjobs.push_back(j);
     b.train_lds = std::max(b.train_lds, train_lds_bytes(p->window, j.M2, j.K, j.cap));
@@ -178,11 +198,14 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
   }
 
   b.off_t = 0;
-  b.off_p = align256(b.off_t + b.tjobs.size() * sizeof(TrainJob));
+  b.off_rj = align256(b.off_t + b.tjobs.size() * sizeof(TrainJob));
+  b.off_ri = align256(b.off_rj + b.rjobs.size() * sizeof(TrainJob));
+  b.off_p = align256(b.off_ri + b.ritems.size() * sizeof(int4));
   b.off_d = align256(b.off_p + b.pjobs.size() * sizeof(PackJob));
   b.off_i = align256(b.off_d + b.djobs.size() * sizeof(DetJob));
   b.off_c = align256(b.off_i + b.ditems.size() * sizeof(int2));
-  b.bytes = b.off_c + 256;
+  b.off_rows = b.off_c + 256;                 // tables end here (the bound image)
+  b.bytes = b.off_rows + b.rows_floats * sizeof(float);
   b.signature = signature_of(b.items);
   bool pers = true;
   if (tuned_choice(b.signature, &pers)) b.persistent = pers;
@@ -240,13 +263,24 @@ size_t apsm_batch_workspace_bytes(const apsm_batch_t* b) { return b ? b->bytes :
 int apsm_batch_bind(apsm_batch_t* b, void* workspace, size_t bytes, void* stream) {
   if (!b || !workspace) return APSM_ERR_INVALID_ARG;
   if (bytes < b->bytes || (reinterpret_cast<uintptr_t>(workspace) & 255)) return APSM_ERR_INVALID_ARG;
-  std::vector<unsigned char> img(b->bytes, 0);
+  // the tables (the kernel rows after them are written on the device)
+  std::vector<unsigned char> img(b->off_rows, 0);
   if (!b->tjobs.empty()) std::memcpy(img.data() + b->off_t, b->tjobs.data(), b->tjobs.size() * sizeof(TrainJob));
+  if (!b->rjobs.empty()) {
+    std::vector<TrainJob> rj = b->rjobs;
+    float* rows = reinterpret_cast<float*>(static_cast<unsigned char*>(workspace) + b->off_rows);
+    for (size_t q = 0; q < rj.size(); ++q) {
+      rj[q].glag = rows + b->rows_off[q];
+      rj[q].kw = rj[q].glag + (size_t)2 * rj[q].P * rj[q].cap;
+    }
+    std::memcpy(img.data() + b->off_rj, rj.data(), rj.size() * sizeof(TrainJob));
+  }
+  if (!b->ritems.empty()) std::memcpy(img.data() + b->off_ri, b->ritems.data(), b->ritems.size() * sizeof(int4));
   if (!b->pjobs.empty()) std::memcpy(img.data() + b->off_p, b->pjobs.data(), b->pjobs.size() * sizeof(PackJob));
   if (!b->djobs.empty()) std::memcpy(img.data() + b->off_d, b->djobs.data(), b->djobs.size() * sizeof(DetJob));
   if (!b->ditems.empty()) std::memcpy(img.data() + b->off_i, b->ditems.data(), b->ditems.size() * sizeof(int2));
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(workspace, img.data(), b->bytes, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(workspace, img.data(), img.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_status(e);
   b->ws = static_cast<unsigned char*>(workspace);
@@ -254,10 +288,22 @@ int apsm_batch_bind(apsm_batch_t* b, void* workspace, size_t bytes, void* stream
   return APSM_OK;
 }
 
+int apsm_batch_kernel_rows(const apsm_batch_t* b, void* stream) {
+  if (!b || !b->ws) return APSM_ERR_INVALID_ARG;
+  return hip_status(launch_kernel_rows(at<TrainJob>(b, b->off_rj), at<int4>(b, b->off_ri), (int)b->ritems.size(),
+                                       b->rows_max_m2, b->cm, (hipStream_t)stream));
+}
+
 int apsm_batch_train(const apsm_batch_t* b, void* stream) {
+  if (int rc = apsm_batch_kernel_rows(b, stream)) return rc;
+  return apsm_batch_train_prepared(b, stream);
+}
+
+int apsm_batch_train_prepared(const apsm_batch_t* b, void* stream) {
   if (!b || !b->ws) return APSM_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_train_table(at<TrainJob>(b, b->off_t), (int)b->tjobs.size(), b->cm, b->train_lds, s);
+  hipError_t e = launch_train_rows(at<TrainJob>(b, b->off_rj), (int)b->rjobs.size(), b->cm, b->rows_lds, s);
+  if (e == hipSuccess) e = launch_train_table(at<TrainJob>(b, b->off_t), (int)b->tjobs.size(), b->cm, b->train_lds, s);
   if (e == hipSuccess) e = launch_pack_model_batch(at<PackJob>(b, b->off_p), (int)b->pjobs.size(), b->pack_max_cap, s);
   for (size_t q = 0; q < b->train_plain.size() && e == hipSuccess; ++q) {
     // shapes outside the table kernel (2M > 64): one launch each, no packed form

@@ -170,9 +170,10 @@ __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
 
 // Component m of r_n (zero in the padding m >= M2):
 // r_{2t} = r1(t) = x_t, r_{2t+1} = r2(t) = [x_{t,M..2M-1}; -x_{t,0..M-1}].
-__device__ __forceinline__ float sample_comp(const float* rx, int M2, int M, int n, int m) {
+template <class Ptr>
+__device__ __forceinline__ float sample_comp(Ptr rx, int M2, int M, int n, int m) {
   if (m >= M2) return 0.0f;
-  const float* src = rx + (size_t)(n >> 1) * M2;
+  const auto src = rx + (size_t)(n >> 1) * M2;
   if ((n & 1) == 0) return src[m];
   return m < M ? src[m + M] : -src[m - M];
 }
@@ -184,6 +185,12 @@ __device__ __forceinline__ int ring_sub(int a, int b, int mod) {
 }
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) int32_t gint;
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* to_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
 
 // NST steps of a member product from member q0 on: every operand load
 // first, then the products, in straight-line code so that the loads issue
@@ -242,22 +249,32 @@ __device__ __forceinline__ floatx4 member_product(floatx4 acc, int L, int grp, c
 }
 
 // Training of one detector by one workgroup of kThreads threads.  lds_raw
-// holds lds_floats(W, KP, M2P) floats.
-template <int M2P, int KP, int SLOTS>
+// holds lds_floats(W, KP, M2P) floats.  ROWS (with SLOTS > 0): the kernel
+// values of each step come from the precomputed rows j.glag and j.kw instead
+// of being evaluated against a dictionary held here; the dictionary is
+// written from the pilots at the end.
+template <int M2P, int KP, int SLOTS, bool ROWS = false>
 __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon& cm, float* lds_raw,
                                            int* block_flags_p) {
+  static_assert(!ROWS || SLOTS > 0, "rows training keeps the coefficients in registers");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int W = cm.W, R = W + 1, cap = j.cap, K = j.K, M2 = j.M2, M = j.M2 / 2;
   const int T = 2 * j.P;
   const int EVS = W > 1 ? W - 1 : 1;
   Lds s = carve(lds_raw, W, KP, M2P);
-  const float* rx = j.rx;
-  const float* sym = j.sym;
-  float* const dict = j.dict;
-  float* const alpha = j.alpha;
-  float* const wout = j.w;
-  int32_t* const state = j.state;
+  // The job's arrays are global memory.  Saying so makes their accesses
+  // global (not flat) instructions, which the LDS wait counter does not
+  // track: the loads issued ahead of their use are then not drained by the
+  // LDS waits of every phase.
+  const gfloat* rx = to_global(j.rx);
+  const gfloat* sym = to_global(j.sym);
+  gfloat* const dict = to_global(j.dict);
+  gfloat* const alpha = to_global(j.alpha);
+  gfloat* const wout = to_global(j.w);
+  gint* const state = to_global(j.state);
+  const gfloat* const glag = to_global(j.glag);
+  const gfloat* const kwg = to_global(j.kw);
   int& block_flags = *block_flags_p;
 
   for (int i = tid; i < W * KP; i += kThreads) {
@@ -297,17 +314,23 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   floatx4 wacc = {0.0f, 0.0f, 0.0f, 0.0f};
 
   // Register-resident slots (SLOTS > 0): slot tid + kThreads * u.
-  float dreg[SLOTS > 0 ? SLOTS : 1][M2P];
-  float dnorm[SLOTS > 0 ? SLOTS : 1];
+  constexpr int DS = SLOTS > 0 && !ROWS ? SLOTS : 1;     // slots whose vectors are held here
+  float dreg[DS][ROWS ? 1 : M2P];
+  float dnorm[DS];
   float areg[SLOTS > 0 ? SLOTS : 1][KP];
   if constexpr (SLOTS > 0) {
 #pragma unroll
     for (int u = 0; u < SLOTS; ++u) {
-      dnorm[u] = 0.0f;
-#pragma unroll
-      for (int m = 0; m < M2P; ++m) dreg[u][m] = 0.0f;
 #pragma unroll
       for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
+    }
+    if constexpr (!ROWS) {
+#pragma unroll
+      for (int u = 0; u < SLOTS; ++u) {
+        dnorm[u] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < M2P; ++m) dreg[u][m] = 0.0f;
+      }
     }
   } else if constexpr (SLOTS == 0) {
     // Dictionary in the model buffer, coefficients in LDS; start from an empty one.
@@ -321,28 +344,60 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 
   // Global inputs are read one step ahead, so their latency overlaps the
   // previous step: component tid of r_{n+1} (stored into the vector ring in
-  // phase C) and b_{k,n+1} for thread k.
-  float comp_nx = 0.0f, bv = 0.0f, bv_nx = 0.0f;
+  // phase C) and b_{k,n+1} for thread k.  Every load of the step loop is
+  // unconditional (clamped indices; the sign of an r2 component and the
+  // user mask are applied where the value is stored), so that the waits the
+  // compiler places for each value cover only that value's load.
+  float comp_nx = 0.0f, comp_sg = 0.0f, bv = 0.0f, bv_nx = 0.0f;
   if (tid < M2P) {
     const float c0 = sample_comp(rx, M2, M, 0, tid);
     s.rwin[tid] = c0;
     s.rwin[R * M2P + tid] = c0;
   }
-  bv = tid < K ? sym[tid * 2] : 0.0f;
+  bv = sym[(tid < K ? tid : 0) * 2];
+
+  // Rows training: the kernel values of the even steps are loaded into
+  // kr0 / kw0, those of the odd steps into kr1 / kw1, each two steps ahead
+  // of its use.  Thread t reads, per slot, the lag that slot has at that
+  // step, and for t < W the window Gram entry of lag t.
+  float kr0[ROWS ? SLOTS : 1], kr1[ROWS ? SLOTS : 1];
+  float kw0 = 0.0f, kw1 = 0.0f;
+  auto rows_load = [&](int m, int sm, float* kr, float& kwv) {
+    const gfloat* grow = glag + (size_t)m * cap;
+#pragma unroll
+    for (int u = 0; u < (ROWS ? SLOTS : 1); ++u) {
+      const int slot = tid + kThreads * u;
+      kr[u] = grow[ring_sub(sm, slot < cap ? slot : 0, cap)];
+    }
+    kwv = kwg[(size_t)m * W + (tid < W ? tid : 0)];
+  };
+  int sn2 = 0;                              // (n + 2) % cap
+  if constexpr (ROWS) {
+    rows_load(0, 0, kr0, kw0);
+    rows_load(T > 1 ? 1 : 0, 1 % cap, kr1, kw1);
+    sn2 = 2 % cap;
+  }
   __syncthreads();
 
   int sn = 0, nw = 0, nr = 0;               // n % cap, n % W, n % R
-  for (int n = 0; n < T; ++n) {
-    if (n + 1 < T) {
-      comp_nx = tid < M2P ? sample_comp(rx, M2, M, n + 1, tid) : 0.0f;
-      bv_nx = tid < K ? sym[((size_t)((n + 1) >> 1) * K + tid) * 2 + ((n + 1) & 1)] : 0.0f;
+  // One training step; kr / kwv: the prefetched kernel values of this step
+  // (rows training), refilled with those of step n + 2 once used.
+  auto step = [&](const int n, float* kr, float& kwv) {
+    {
+      const int n1 = n + 1 < T ? n + 1 : n;   // the last step reloads its own sample (unused)
+      const int m = tid < M2 ? tid : 0;
+      const bool odd = (n1 & 1) != 0;
+      comp_nx = rx[(size_t)(n1 >> 1) * M2 + (odd ? (m < M ? m + M : m - M) : m)];
+      comp_sg = tid < M2 ? (odd && m >= M ? -1.0f : 1.0f) : 0.0f;
+      bv_nx = sym[((size_t)(n1 >> 1) * K + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
     }
 
     // ------------------------------------------------------------ phase A
     const float* rrow = s.rwin + nr * M2P;  // r_n
-    float rn[SLOTS > 0 ? M2P : 1];
+    float rn[SLOTS > 0 && !ROWS ? M2P : 1];
     float nn = 0.0f;
-    if constexpr (SLOTS > 0) {
+    if constexpr (ROWS) {
+    } else if constexpr (SLOTS > 0) {
 #pragma unroll
       for (int m = 0; m < M2P; ++m) {
         rn[m] = rrow[m];
@@ -354,8 +409,18 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     const bool evicting = n >= cap;
     const int L = n + 1 < W ? n + 1 : W;    // |J_n|
     const int evlo = n - cap + 1;           // oldest entry in the dictionary after the append
-    if (tid < KP) s.bwin[nw * KP + tid] = bv;
-    if (tid == 0) {
+    if (tid < KP) s.bwin[nw * KP + tid] = tid < K ? bv : 0.0f;
+    if constexpr (ROWS) {
+      // Gram entries of r_n against the window members, one lag per thread
+      if (tid < L) {
+        const int ir = ring_sub(nr, tid, R);
+        s.gram[nr * 2 * R + ir] = kwv;
+        s.gram[nr * 2 * R + ir + R] = kwv;
+        s.gram[ir * 2 * R + nr] = kwv;
+        s.gram[ir * 2 * R + nr + R] = kwv;
+      }
+      if (tid == 0) s.ikjj[nw] = kwv > 0.0f ? 1.0f / kwv : 0.0f;   // lag 0: K(r_n, r_n)
+    } else if (tid == 0) {
       const float kjj = fmaf(cm.wl, nn, cm.wg);
       s.ikjj[nw] = kjj > 0.0f ? 1.0f / kjj : 0.0f;
     }
@@ -363,13 +428,32 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     float part[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) part[k] = 0.0f;
-    if (wowner) {
-      const float rm = cm.wl * rrow[wm];
-#pragma unroll
-      for (int k = 0; k < KP; ++k) part[k] += (grp == (k >> 2)) ? wacc[k & 3] * rm : 0.0f;
-    }
 
-    if constexpr (SLOTS > 0) {
+    if constexpr (ROWS) {
+#pragma unroll
+      for (int u = 0; u < SLOTS; ++u) {
+        const int slot = tid + kThreads * u;
+        if (slot == sn) {                    // append (and evict)
+          if (evicting) {
+#pragma unroll
+            for (int k = 0; k < KP; ++k) s.aev[k] = areg[u][k];
+          }
+#pragma unroll
+          for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
+        }
+        if (slot < cap && slot <= n) {
+          const int back = ring_sub(sn, slot, cap);   // this slot holds sample n - back
+          const float kg = kr[u];
+#pragma unroll
+          for (int k = 0; k < KP; ++k) part[k] = fmaf(areg[u][k], kg, part[k]);
+          const int mv = n - back - evlo;
+          if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
+        }
+      }
+      // this buffer's next use is step n + 2
+      rows_load(n + 2 < T ? n + 2 : n, sn2, kr, kwv);   // past the end: a valid row, unused
+      sn2 = sn2 + 1 == cap ? 0 : sn2 + 1;
+    } else if constexpr (SLOTS > 0) {
 #pragma unroll
       for (int u = 0; u < SLOTS; ++u) {
         const int slot = tid + kThreads * u;
@@ -420,7 +504,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
             for (int k = 0; k < KP; ++k) s.aev[k] = s.alds[k * cap + sn];
           for (int k = 0; k < KP; ++k) s.alds[k * cap + sn] = 0.0f;
         } else {
-          float* arow = alpha + (size_t)sn * K;
+          auto arow = alpha + (size_t)sn * K;
           if (evicting)
             for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
           for (int k = 0; k < K; ++k) arow[k] = 0.0f;
@@ -439,7 +523,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
             for (int k = 0; k < KP; ++k) av[b][k] = ok ? s.alds[k * cap + slot] : 0.0f;
           } else {
-            const float* arow = alpha + (size_t)(ok ? slot : 0) * K;
+            const auto arow = alpha + (size_t)(ok ? slot : 0) * K;
 #pragma unroll
             for (int k = 0; k < KP; ++k) av[b][k] = (ok && k < K) ? arow[k] : 0.0f;
           }
@@ -453,7 +537,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
           for (int b = 0; b < SB; ++b) {
             const int slot = base + b * kThreads;
-            const float* dcol = dict + (slot < nslot ? slot : 0);
+            const auto dcol = dict + (slot < nslot ? slot : 0);
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
               const int mm = m0 + m < M2 ? m0 + m : M2 - 1;
@@ -491,6 +575,14 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
           if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
         }
       }
+    }
+    // the linear part last: the weight tile is the accumulator of the
+    // previous step's matrix-core products, which the slot work above
+    // leaves time to complete
+    if (wowner) {
+      const float rm = cm.wl * rrow[wm];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) part[k] += (grp == (k >> 2)) ? wacc[k & 3] * rm : 0.0f;
     }
     {
       const float v = wave_sum_scatter<KP>(part, lane);
@@ -542,8 +634,8 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     }
     if (tid < M2P && n + 1 < T) {           // r_{n+1} into its ring row (no member of J_n)
       const int nr1 = nr + 1 == R ? 0 : nr + 1;
-      s.rwin[nr1 * M2P + tid] = comp_nx;
-      s.rwin[(nr1 + R) * M2P + tid] = comp_nx;
+      s.rwin[nr1 * M2P + tid] = comp_sg * comp_nx;
+      s.rwin[(nr1 + R) * M2P + tid] = comp_sg * comp_nx;
     }
     __syncthreads();
 
@@ -595,6 +687,16 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     sn = sn + 1 == cap ? 0 : sn + 1;
     nw = nw + 1 == W ? 0 : nw + 1;
     nr = nr + 1 == R ? 0 : nr + 1;
+  };
+  if constexpr (ROWS) {
+    // two steps per iteration, each with its own buffer, so that a buffer is
+    // refilled right after its use and next read two steps later
+    for (int n = 0; n < T; n += 2) {
+      step(n, kr0, kw0);
+      if (n + 1 < T) step(n + 1, kr1, kw1);
+    }
+  } else {
+    for (int n = 0; n < T; ++n) step(n, kr0, kw0);
   }
   __syncthreads();
 
@@ -604,10 +706,18 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     for (int u = 0; u < SLOTS; ++u) {
       const int slot = tid + kThreads * u;
       if (slot < cap) {
+        if constexpr (ROWS) {
+          // the slot holds sample T-1 - lag (lag of the slot after the last step), if written
+          const int lag = ring_sub((T - 1) % cap, slot, cap);
+          const int i = T - 1 - lag;
+          for (int mm = 0; mm < M2; ++mm)
+            dict[(size_t)mm * cap + slot] = i >= 0 ? sample_comp(rx, M2, M, i, mm) : 0.0f;
+        } else {
 #pragma unroll
-        for (int mm = 0; mm < M2P; ++mm)
-          if (mm < M2) dict[(size_t)mm * cap + slot] = dreg[u][mm];
-        float* arow = alpha + (size_t)slot * K;
+          for (int mm = 0; mm < M2P; ++mm)
+            if (mm < M2) dict[(size_t)mm * cap + slot] = dreg[u][mm];
+        }
+        auto arow = alpha + (size_t)slot * K;
 #pragma unroll
         for (int k = 0; k < KP; ++k)
           if (k < K) arow[k] = areg[u][k];
@@ -730,6 +840,89 @@ __global__ __launch_bounds__(kThreads) void train_table_kernel(const TrainJob* j
   }
 }
 
+// ---- training from precomputed kernel rows
+
+// Every rows specialisation (M2P, KP, SLOTS in 1, 2, 4, 8) with its number.
+#define APSM_ROWS_VARIANTS_M(X, base, M2P, KP) \
+  X(base + 0, M2P, KP, 1) X(base + 1, M2P, KP, 2) X(base + 2, M2P, KP, 4) X(base + 3, M2P, KP, 8)
+#define APSM_ROWS_VARIANTS(X)                                                     \
+  APSM_ROWS_VARIANTS_M(X, 0, 16, 4) APSM_ROWS_VARIANTS_M(X, 4, 16, 8)            \
+  APSM_ROWS_VARIANTS_M(X, 8, 16, 16) APSM_ROWS_VARIANTS_M(X, 12, 32, 4)          \
+  APSM_ROWS_VARIANTS_M(X, 16, 32, 8) APSM_ROWS_VARIANTS_M(X, 20, 32, 16)         \
+  APSM_ROWS_VARIANTS_M(X, 24, 64, 4) APSM_ROWS_VARIANTS_M(X, 28, 64, 8)          \
+  APSM_ROWS_VARIANTS_M(X, 32, 64, 16) APSM_ROWS_VARIANTS_M(X, 36, 128, 4)        \
+  APSM_ROWS_VARIANTS_M(X, 40, 128, 8) APSM_ROWS_VARIANTS_M(X, 44, 128, 16)
+
+__global__ __launch_bounds__(kThreads) void train_rows_kernel(const TrainJob* jobs, TrainCommon cm) {
+  extern __shared__ float lds_raw[];
+  __shared__ int block_flags;
+  const TrainJob j = jobs[blockIdx.x];
+  switch (j.variant) {
+#define APSM_ROWS_CASE(id, M2P, KP, SLOTS) \
+  case id: train_body<M2P, KP, SLOTS, true>(j, cm, lds_raw, &block_flags); break;
+    APSM_ROWS_VARIANTS(APSM_ROWS_CASE)
+#undef APSM_ROWS_CASE
+    default:
+      break;
+  }
+}
+
+// Kernel rows of kRowsTile training steps and kRowsLags lags per
+// workgroup: item (job, n0, l0) writes, for n0 <= n < n0 + kRowsTile and
+// l0 <= l < l0 + kRowsLags (thread l - l0), glag[n][l] = kappa_G(r_n, r_{n-l})
+// (0 for l > n), from the squared distance accumulated component by
+// component, and for l < W the window Gram entry
+// kw[n][l] = wL r_n.r_{n-l} + wG kappa_G(r_n, r_{n-l}).  The tile's steps
+// and the samples r_{n-l} it needs are staged in LDS first (sample rows at
+// an odd stride, so that the lanes' strided reads hit distinct banks).
+constexpr int kRowsTile = 16;
+constexpr int kRowsLags = 256;
+constexpr int kRowsSamples = kRowsTile + kRowsLags - 1;
+
+size_t kernel_rows_lds_floats(int M2) { return (size_t)kRowsTile * M2 + (size_t)kRowsSamples * (M2 + 1); }
+
+__global__ __launch_bounds__(kRowsLags) void kernel_rows_kernel(const TrainJob* jobs, const int4* items,
+                                                                TrainCommon cm) {
+  extern __shared__ float rows_lds[];
+  const int4 it = items[blockIdx.x];
+  const TrainJob& j = jobs[it.x];
+  const int n0 = it.y, l0 = it.z;
+  const int M2 = j.M2, M = M2 / 2, cap = j.cap, W = cm.W, T = 2 * j.P, S = M2 + 1;
+  float* rs = rows_lds;                                  // [kRowsTile][M2] steps n0..
+  float* xs = rows_lds + kRowsTile * M2;                 // [kRowsSamples][S] samples ilo..
+  const int ilo = n0 - l0 - (kRowsLags - 1);
+  for (int e = threadIdx.x; e < kRowsTile * M2; e += kRowsLags) {
+    const int r = e / M2, m = e - r * M2, n = n0 + r;
+    rs[e] = n < T ? sample_comp(to_global(j.rx), M2, M, n, m) : 0.0f;
+  }
+  for (int e = threadIdx.x; e < kRowsSamples * M2; e += kRowsLags) {
+    const int q = e / M2, m = e - q * M2, i = ilo + q;
+    xs[q * S + m] = (i >= 0 && i < T) ? sample_comp(to_global(j.rx), M2, M, i, m) : 0.0f;
+  }
+  __syncthreads();
+  const int l = l0 + threadIdx.x;
+  if (l >= cap) return;
+  for (int r = 0; r < kRowsTile; ++r) {
+    const int n = n0 + r;
+    if (n >= T) break;
+    const int i = n - l;
+    float kg = 0.0f, dot = 0.0f;
+    if (i >= 0) {
+      const float* a = rs + r * M2;
+      const float* x = xs + (i - ilo) * S;
+      float d2 = 0.0f;
+      for (int m = 0; m < M2; ++m) {
+        const float d = a[m] - x[m];
+        d2 = fmaf(d, d, d2);
+        dot = fmaf(a[m], x[m], dot);
+      }
+      kg = __builtin_amdgcn_exp2f(-j.c2 * d2);
+    }
+    to_global(j.glag)[(size_t)n * cap + l] = kg;
+    if (l < W) to_global(j.kw)[(size_t)n * W + l] = i >= 0 ? fmaf(cm.wl, dot, cm.wg * kg) : 0.0f;
+  }
+}
+
 template <int M2P, int KP, int SLOTS>
 hipError_t launch_one(const TrainArgs& a, hipStream_t stream) {
   const size_t bytes = lds_bytes_for(a.cm.W, KP, M2P, SLOTS, a.cap);
@@ -781,6 +974,42 @@ static int table_slots(int M2, int K, int W, int cap) {
 }
 
 bool train_in_table(int M2) { return M2 <= 64; }
+
+int train_rows_variant(int M2, int K, int cap) {
+  const int need = (cap + kThreads - 1) / kThreads;
+  if (M2 > 128 || K > 16 || need > 8) return -1;
+  const int M2P = m2p_for(M2), KP = kp_for(K);
+  const int mi = M2P == 16 ? 0 : M2P == 32 ? 1 : M2P == 64 ? 2 : 3;
+  const int ki = KP == 4 ? 0 : KP == 8 ? 1 : 2;
+  const int si = need <= 1 ? 0 : need <= 2 ? 1 : need <= 4 ? 2 : 3;
+  return (mi * 3 + ki) * 4 + si;
+}
+
+size_t train_rows_lds_bytes(int W, int M2, int K) { return lds_floats(W, kp_for(K), m2p_for(M2)) * sizeof(float); }
+
+int kernel_rows_tile_steps() { return kRowsTile; }
+int kernel_rows_tile_lags() { return kRowsLags; }
+
+hipError_t launch_kernel_rows(const TrainJob* jobs, const int4* items, int n_items, int max_M2,
+                              const TrainCommon& cm, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  const size_t bytes = kernel_rows_lds_floats(max_M2) * sizeof(float);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel_rows_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kernel_rows_kernel, dim3(n_items), dim3(kRowsLags), bytes, stream, jobs, items, cm);
+  return hipGetLastError();
+}
+
+hipError_t launch_train_rows(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
+                             hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(train_rows_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(train_rows_kernel, dim3(n), dim3(kThreads), lds_bytes, stream, jobs, cm);
+  return hipGetLastError();
+}
 
 int train_variant(int M2, int K, int W, int cap) {
   return variant_of(m2p_for(M2), kp_for(K), table_slots(M2, K, W, cap));
