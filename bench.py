@@ -38,8 +38,8 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 # (profiles/detect_f16_realistic_slot_counters.md).  Valid only for the kernel
 # sources they were taken with; reported as null otherwise.
 MEASURED_TRAFFIC = {
-    "bytes": (138944 + 55296) * 1024,
-    "sources": {"paper_2201_05024_amd/csrc/detect_f16.h": "2b5f97b6a6a665bb0de93898fcacb970bd49cda8",
+    "bytes": (138977 + 55502) * 1024,
+    "sources": {"paper_2201_05024_amd/csrc/detect_f16.h": "5908371f618de0c3b04c177ce06f05ab8e87321b",
                 "paper_2201_05024_amd/csrc/detect_f16_m32.hip": "d4dbc3a03f2d61d0eb05e76f679e0ec7b04f4b6c"},
 }
 

@@ -41,6 +41,7 @@ MIXED = [
     (9, 16, 100, 77, 200, 0.5, "qpsk"),     # K > 8: FP32 detection path
     (16, 64, 64, 300, 100, 0.5, "qam16"),   # 2M = 128
     (2, 20, 50, 1, 40, 0.5, "qpsk"),
+    (3, 4, 40, 70, 5000, 0.5, "qpsk"),     # dict_cap > 4096: trained without kernel rows
 ]
 W = 8
 
@@ -177,6 +178,28 @@ def test_batch_graph_capture_replay():
             assert torch.equal(it.model.alpha, a0), (rep, i)
             assert torch.equal(it.soft, s0) and torch.equal(it.hard, h0), (rep, i)
             assert torch.equal(it.errors, e0), (rep, i)
+
+
+def test_batch_split_training_on_two_streams():
+    """Kernel rows on one stream and training on another, ordered by an event,
+    give the same models as train() on one stream."""
+    insts, caps, sig = make_mixed(seed0=4300)
+    params = A.Params(window=W)
+    b1, items1 = build_batch(insts, caps, sig, params)
+    b1.train()
+    torch.cuda.synchronize()
+    ref = [(it.model.w.clone(), it.model.alpha.clone(), it.model.dict.clone(), it.model.status()) for it in items1]
+    b2, items2 = build_batch(insts, caps, sig, params)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ev = torch.cuda.Event()
+    b2.kernel_rows(s1)
+    ev.record(s1)
+    s2.wait_event(ev)
+    b2.train_prepared(s2)
+    torch.cuda.synchronize()
+    for i, ((w, a, d, st), it) in enumerate(zip(ref, items2)):
+        assert torch.equal(it.model.w, w) and torch.equal(it.model.alpha, a), i
+        assert torch.equal(it.model.dict, d) and it.model.status() == st, i
 
 
 def test_batch_full_mixed_workload_sampled():
