@@ -339,7 +339,7 @@ int apsm_batch_tune(apsm_batch_t* b, void* stream) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError());
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return hip_status(hipGetLastError());
   }
   float best[2] = {0.0f, 0.0f};
@@ -360,8 +360,8 @@ int apsm_batch_tune(apsm_batch_t* b, void* stream) {
     }
     best[form] = tmin;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc != APSM_OK) return rc;
   b->persistent = best[1] <= best[0];
   std::lock_guard<std::mutex> lock(g_tune_mutex);

@@ -46,22 +46,44 @@ __device__ __forceinline__ void pack_row(const float* dict, const float* alpha, 
   D = D < 0 ? 0 : (D > cap ? cap : D);
   const bool valid = i < D;
   const float sc = ldexpf(1.0f, reinterpret_cast<const int*>(out)[0]);
-  _Float16* row = reinterpret_cast<_Float16*>(out + kHeader) + (size_t)i * G::BSTR;
+  // The row (16-byte aligned: header and row stride are multiples of 16) is
+  // assembled in registers, eight halves at a time, and written with
+  // 16-byte stores.
+  half8* row = reinterpret_cast<half8*>(out + kHeader + (size_t)i * G::ROW_B);
   float n = 0.0f;
-#pragma unroll 4
-  for (int m = 0; m < M2P; ++m) {
-    const float d = (valid && m < M2) ? dict[(size_t)m * cap + i] : 0.0f;
-    n = fmaf(d, d, n);
-    _Float16 hi, lo;
-    split_f16(d * sc, hi, lo);
-    row[m] = hi;
-    row[M2P + m] = lo;
+#pragma unroll
+  for (int m0 = 0; m0 < M2P; m0 += 8) {
+    half8 hv, lv;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int m = m0 + v;
+      const float d = (valid && m < M2) ? dict[(size_t)m * cap + i] : 0.0f;
+      n = fmaf(d, d, n);
+      _Float16 hi, lo;
+      split_f16(d * sc, hi, lo);
+      hv[v] = hi;
+      lv[v] = lo;
+    }
+    row[m0 / 8] = hv;
+    row[(M2P + m0) / 8] = lv;
   }
-  for (int v = 0; v < 8; ++v) row[2 * M2P + v] = (_Float16)0.0f;
-  float* co = reinterpret_cast<float*>(out + kHeader + (size_t)capp * G::ROW_B) + (size_t)i * G::CSTR;
-  for (int k = 0; k < G::K4; ++k) co[k] = (valid && k < K) ? alpha[(size_t)i * K + k] : 0.0f;
-  co[G::K4] = n;
-  co[G::K4 + 1] = co[G::K4 + 2] = co[G::K4 + 3] = 0.0f;
+  half8 zero8;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) zero8[v] = (_Float16)0.0f;
+  row[2 * M2P / 8] = zero8;
+  floatx4* co = reinterpret_cast<floatx4*>(out + kHeader + (size_t)capp * G::ROW_B + (size_t)i * G::CSTR * 4);
+#pragma unroll
+  for (int q = 0; q < G::K4 / 4; ++q) {
+    floatx4 c4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = 4 * q + v;
+      c4[v] = (valid && k < K) ? alpha[(size_t)i * K + k] : 0.0f;
+    }
+    co[q] = c4;
+  }
+  floatx4 tail = {n, 0.0f, 0.0f, 0.0f};
+  co[G::K4 / 4] = tail;
 }
 
 template <int M2P, int K>
