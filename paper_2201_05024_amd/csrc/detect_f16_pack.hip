@@ -8,15 +8,22 @@ namespace apsm {
 namespace f16 {
 namespace {
 
+// Global-memory view of a job pointer: accesses through it are global (not
+// flat) instructions.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // One workgroup of 1024 threads: header[0] = exponent placing max |d| in
 // [2^12, 2^13), header[1] = entries in use.
 __device__ __forceinline__ void dict_scale_body(const float* dict, const int32_t* state, int cap, int M2,
                                                 int* header, float* red) {
-  int D = state[0];
+  int D = gmem(state)[0];
   D = D < 0 ? 0 : (D > cap ? cap : D);
   float m = 0.0f;
   for (int c = 0; c < M2; ++c)                      // component c of entries 0..D-1
-    for (int i = threadIdx.x; i < D; i += blockDim.x) m = fmaxf(m, fabsf(dict[(size_t)c * cap + i]));
+    for (int i = threadIdx.x; i < D; i += blockDim.x) m = fmaxf(m, fabsf(gmem(dict)[(size_t)c * cap + i]));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
@@ -42,14 +49,14 @@ __device__ __forceinline__ void pack_row(const float* dict, const float* alpha, 
   using G = Geo<M2P, K>;
   const int capp = cap_pad(cap);
   if (i >= capp) return;
-  int D = state[0];
+  int D = gmem(state)[0];
   D = D < 0 ? 0 : (D > cap ? cap : D);
   const bool valid = i < D;
-  const float sc = ldexpf(1.0f, reinterpret_cast<const int*>(out)[0]);
+  const float sc = ldexpf(1.0f, gmem(reinterpret_cast<const int*>(out))[0]);
   // The row (16-byte aligned: header and row stride are multiples of 16) is
   // assembled in registers, eight halves at a time, and written with
   // 16-byte stores.
-  half8* row = reinterpret_cast<half8*>(out + kHeader + (size_t)i * G::ROW_B);
+  const auto row = gmem(reinterpret_cast<half8*>(out + kHeader + (size_t)i * G::ROW_B));
   float n = 0.0f;
 #pragma unroll
   for (int m0 = 0; m0 < M2P; m0 += 8) {
@@ -57,7 +64,7 @@ __device__ __forceinline__ void pack_row(const float* dict, const float* alpha, 
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int m = m0 + v;
-      const float d = (valid && m < M2) ? dict[(size_t)m * cap + i] : 0.0f;
+      const float d = (valid && m < M2) ? gmem(dict)[(size_t)m * cap + i] : 0.0f;
       n = fmaf(d, d, n);
       _Float16 hi, lo;
       split_f16(d * sc, hi, lo);
@@ -71,14 +78,14 @@ __device__ __forceinline__ void pack_row(const float* dict, const float* alpha, 
 #pragma unroll
   for (int v = 0; v < 8; ++v) zero8[v] = (_Float16)0.0f;
   row[2 * M2P / 8] = zero8;
-  floatx4* co = reinterpret_cast<floatx4*>(out + kHeader + (size_t)capp * G::ROW_B + (size_t)i * G::CSTR * 4);
+  const auto co = gmem(reinterpret_cast<floatx4*>(out + kHeader + (size_t)capp * G::ROW_B + (size_t)i * G::CSTR * 4));
 #pragma unroll
   for (int q = 0; q < G::K4 / 4; ++q) {
     floatx4 c4;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int k = 4 * q + v;
-      c4[v] = (valid && k < K) ? alpha[(size_t)i * K + k] : 0.0f;
+      c4[v] = (valid && k < K) ? gmem(alpha)[(size_t)i * K + k] : 0.0f;
     }
     co[q] = c4;
   }
