@@ -891,14 +891,38 @@ __global__ __launch_bounds__(kRowsLags) void kernel_rows_kernel(const TrainJob* 
   float* rs = rows_lds;                                  // [kRowsTile][M2] steps n0..
   float* xs = rows_lds + kRowsTile * M2;                 // [kRowsSamples][S] samples ilo..
   const int ilo = n0 - l0 - (kRowsLags - 1);
-  for (int e = threadIdx.x; e < kRowsTile * M2; e += kRowsLags) {
-    const int r = e / M2, m = e - r * M2, n = n0 + r;
-    rs[e] = n < T ? sample_comp(to_global(j.rx), M2, M, n, m) : 0.0f;
-  }
-  for (int e = threadIdx.x; e < kRowsSamples * M2; e += kRowsLags) {
-    const int q = e / M2, m = e - q * M2, i = ilo + q;
-    xs[q * S + m] = (i >= 0 && i < T) ? sample_comp(to_global(j.rx), M2, M, i, m) : 0.0f;
-  }
+  // Staging: branch-free loads (clamped sample index; the sign of an r2
+  // component and the validity mask applied at the store) in unrolled
+  // loops, so that several loads are in flight before the first store
+  // waits for its data.
+  const auto rx = to_global(j.rx);
+  auto comp = [&](int i, int m, float& sg) {
+    const bool ok = i >= 0 && i < T, odd = (i & 1) != 0;
+    const int ic = ok ? i : 0;
+    sg = ok ? (odd && m >= M ? -1.0f : 1.0f) : 0.0f;
+    return rx[(size_t)(ic >> 1) * M2 + (odd ? (m < M ? m + M : m - M) : m)];
+  };
+  // element e of a staging region: vector e / M2 (first index i0), component e % M2
+  auto stage = [&](int count, int i0, float* dst, int stride) {
+    constexpr int B = 8;
+    for (int e0 = threadIdx.x; e0 < count; e0 += B * kRowsLags) {
+      float v[B], sg[B];
+      int at[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = e0 + u * kRowsLags;
+        const int ec = e < count ? e : e0;
+        const int q = ec / M2, m = ec - q * M2;
+        v[u] = comp(i0 + q, m, sg[u]);
+        at[u] = e < count ? q * stride + m : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (at[u] >= 0) dst[at[u]] = sg[u] * v[u];
+    }
+  };
+  stage(kRowsTile * M2, n0, rs, M2);
+  stage(kRowsSamples * M2, ilo, xs, S);
   __syncthreads();
   const int l = l0 + threadIdx.x;
   if (l >= cap) return;
