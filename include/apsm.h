@@ -50,6 +50,18 @@ extern "C" {
 #define APSM_ERR_SHAPE          2  /* sizes inconsistent with each other or the model    */
 #define APSM_ERR_UNSUPPORTED    3  /* valid but beyond this build's limits (see below)   */
 #define APSM_ERR_HIP            4  /* a HIP launch failed; see apsm_last_hip_error()     */
+#define APSM_ERR_WORKSPACE      5  /* workspace NULL, smaller than required or not
+                                      256-byte aligned                                   */
+#define APSM_ERR_NONFINITE      6  /* apsm_get_status: a model status flag reports
+                                      non-finite values (see APSM_FLAG_*)                */
+
+/* Status flags in state[3] of a model (apsm_model_t).  Training overwrites
+ * the word with its own flags; detection ORs its flag in (atomically, so
+ * concurrent detections with one model are safe) and leaves every other
+ * model field untouched.  A caller may clear the word by writing 0. */
+#define APSM_FLAG_TRAIN_NONFINITE   1  /* a training prediction error was not finite    */
+#define APSM_FLAG_DETECT_NONFINITE  2  /* detection met a non-finite received vector
+                                          component or produced a non-finite output    */
 
 /* ---- limits of this build ------------------------------------------- */
 #define APSM_MAX_M2       128      /* real input dimension 2M                       */
@@ -101,8 +113,9 @@ typedef struct apsm_params {
  *                         unused slots.
  *  w      [K][M2]         linear coefficients (wL * gamma^(L) of Sec. II-D).
  *  state  int32[4]        written by training: {entries in use, next slot,
- *                         training steps done, status flags}; flag bit 0 =
- *                         non-finite training input seen.
+ *                         training steps done, status flags (APSM_FLAG_*)};
+ *                         detection only ORs APSM_FLAG_DETECT_NONFINITE into
+ *                         the flags word.
  *  packed apsm_model_packed_bytes(M2, K, dict_cap) bytes: the same filter
  *         re-laid out for the detection kernels (written by apsm_train and by
  *         apsm_model_pack, read by apsm_detect).  Required when that size is
@@ -157,7 +170,9 @@ int apsm_train_batched(const apsm_params_t* params, int M2, int K, int P, int n_
                        const apsm_model_t* models, void* stream);
 
 /* Detection (Sec. III-B): for every received vector r(s), s = 0..S-1,
- * g_k = f_k(r1) + i f_k(r2) with the frozen filter `model` (read only).
+ * g_k = f_k(r1) + i f_k(r2) with the frozen filter `model` (read only, except
+ * that APSM_FLAG_DETECT_NONFINITE is ORed into state[3] when a received
+ * vector component or an output is not finite; outputs are still written).
  *  model      HOST struct of a trained model.
  *  sigma2     the kernel width the model was trained with (> 0).
  *  S          number of received vectors, >= 0 (0 launches nothing).
@@ -213,7 +228,11 @@ typedef struct apsm_batch apsm_batch_t;   /* opaque host object */
  * w_gauss, window and pos_weights shared by all of them; its sigma2 and
  * dict_cap are not used (each item has its own).  Every item must satisfy
  * what apsm_train and apsm_detect require of the same arguments, and
- * model.dict_cap >= window.  On success *out is a new batch. */
+ * model.dict_cap >= window.  The buffers the batch writes (every item's model
+ * arrays, soft, hard and err_count) must not overlap each other, and no
+ * buffer it reads (pilots, rx, truth) may overlap one it writes: such a
+ * batch is rejected with APSM_ERR_INVALID_ARG.  On success *out is a new
+ * batch. */
 int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* items, int n,
                       apsm_batch_t** out);
 
@@ -227,7 +246,8 @@ size_t apsm_batch_workspace_bytes(const apsm_batch_t* batch);
 /* Write the batch's tables into `workspace` (DEVICE, at least
  * apsm_batch_workspace_bytes, 256-byte aligned, caller-owned; it must not be
  * used for anything else while the batch is used).  Synchronous: returns
- * after the copy on `stream` has completed. */
+ * after the copy on `stream` has completed.  APSM_ERR_WORKSPACE if the
+ * workspace is NULL, too small or misaligned. */
 int apsm_batch_bind(apsm_batch_t* batch, void* workspace, size_t bytes, void* stream);
 
 /* Time the launch forms of batched detection on this batch (persistent
@@ -299,7 +319,8 @@ size_t apsm_unrolled_workspace_bytes(const apsm_unrolled_t* u);
 /* Forward: loss (DEVICE float[1]) = L.  Inputs, contiguous DEVICE arrays:
  *  rx_pilot [n][P][M2], sym_pilot [n][P][K][2], rx_val [n][S][M2],
  *  sym_val [n][S][K][2].  workspace: >= apsm_unrolled_workspace_bytes,
- *  256-byte aligned; keeps what the backward call needs. */
+ *  256-byte aligned (else APSM_ERR_WORKSPACE); keeps what the backward call
+ *  needs. */
 int apsm_unrolled_forward(const apsm_unrolled_t* u, const float* theta, const float* rx_pilot,
                           const float* sym_pilot, const float* rx_val, const float* sym_val,
                           void* workspace, size_t ws_bytes, float* loss, void* stream);
@@ -313,8 +334,16 @@ int apsm_unrolled_backward(const apsm_unrolled_t* u, const float* theta, const f
                            void* stream);
 
 /* Synchronous copy of model->state into host_state[4]; waits for all work on
- * the device. */
+ * the device.  Returns APSM_ERR_NONFINITE (with host_state filled) when the
+ * flags word host_state[3] is nonzero, APSM_OK otherwise. */
 int apsm_get_status(const apsm_model_t* model, int32_t* host_state);
+
+/* Release what the library keeps on the host between calls: the launch-form
+ * and tile choices cached by apsm_batch_tune.  Device memory is not touched
+ * (the library holds none besides its static scratch array).  Safe to call at
+ * any time from one thread while no other library call runs; later calls
+ * work as after loading the library. */
+void apsm_shutdown(void);
 
 /* Static description of an error code; never NULL. */
 const char* apsm_strerror(int code);

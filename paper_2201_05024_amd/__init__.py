@@ -13,11 +13,14 @@ from dataclasses import dataclass
 from typing import Optional, Sequence
 
 __all__ = ["Params", "Model", "train", "train_batched", "detect", "Batch", "BatchItem", "APSMError",
-           "unrolled_loss", "APSMUnrolled", "library", "LIB_PATH", "MOD_NONE", "MOD_QPSK", "MOD_QAM16"]
+           "unrolled_loss", "APSMUnrolled", "library", "shutdown", "LIB_PATH", "MOD_NONE", "MOD_QPSK",
+           "MOD_QAM16", "ERR_WORKSPACE", "ERR_NONFINITE", "FLAG_TRAIN_NONFINITE", "FLAG_DETECT_NONFINITE"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapsm.so")
 
 MOD_NONE, MOD_QPSK, MOD_QAM16 = 0, 2, 4
+ERR_INVALID_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_HIP, ERR_WORKSPACE, ERR_NONFINITE = 1, 2, 3, 4, 5, 6
+FLAG_TRAIN_NONFINITE, FLAG_DETECT_NONFINITE = 1, 2
 _MODS = {None: MOD_NONE, "none": MOD_NONE, "qpsk": MOD_QPSK, "qam16": MOD_QAM16,
          MOD_NONE: MOD_NONE, MOD_QPSK: MOD_QPSK, MOD_QAM16: MOD_QAM16}
 
@@ -119,6 +122,8 @@ def library() -> ctypes.CDLL:
         L.apsm_last_hip_error.restype = ctypes.c_char_p
         L.apsm_version.argtypes = []
         L.apsm_version.restype = ctypes.c_char_p
+        L.apsm_shutdown.argtypes = []
+        L.apsm_shutdown.restype = None
         _lib = L
     return _lib
 
@@ -200,12 +205,20 @@ class Model:
         return self
 
     def status(self):
+        """The model's state words (synchronises the device).  'flags' holds
+        FLAG_TRAIN_NONFINITE / FLAG_DETECT_NONFINITE bits; their presence is
+        reported here, not raised."""
         out = (ctypes.c_int32 * 4)()
         m = self._c()
         rc = library().apsm_get_status(ctypes.byref(m), out)
-        if rc:
+        if rc and rc != ERR_NONFINITE:
             raise APSMError(rc, "apsm_get_status")
         return {"size": out[0], "head": out[1], "steps": out[2], "flags": out[3]}
+
+
+def shutdown() -> None:
+    """Release the library's host-side caches (apsm_shutdown)."""
+    library().apsm_shutdown()
 
 
 def train(rx_pilot, sym_pilot, params: Params, model: Optional[Model] = None, stream=None) -> Model:

@@ -82,6 +82,7 @@ DetectArgs detect_args(const apsm_model_t* model, float sigma2, int S, const flo
   a.alpha = model->alpha;
   a.w = model->w;
   a.state = model->state;
+  a.flags = model->state + 3;
   a.packed = static_cast<const unsigned char*>(model->packed);
   a.rx = rx;
   a.soft = soft;
@@ -111,6 +112,8 @@ const char* apsm_strerror(int code) {
     case APSM_ERR_SHAPE: return "inconsistent sizes";
     case APSM_ERR_UNSUPPORTED: return "size beyond the limits of this build";
     case APSM_ERR_HIP: return "HIP runtime error (see apsm_last_hip_error)";
+    case APSM_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case APSM_ERR_NONFINITE: return "non-finite values flagged in the model status";
     default: return "unknown status code";
   }
 }
@@ -214,7 +217,8 @@ int apsm_get_status(const apsm_model_t* model, int32_t* host_state) {
   if (!host_state) return APSM_ERR_INVALID_ARG;
   hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(host_state, model->state, 4 * sizeof(int32_t), hipMemcpyDeviceToHost);
-  return hip_status(e);
+  if (e != hipSuccess) return hip_status(e);
+  return host_state[3] != 0 ? APSM_ERR_NONFINITE : APSM_OK;
 }
 
 }  // extern "C"

@@ -63,6 +63,7 @@ struct DetectArgs {
   const float* alpha;     // [cap][K]
   const float* w;         // [K][M2]
   const int32_t* state;   // [4], state[0] = entries in use
+  int32_t* flags;         // state + 3: APSM_FLAG_DETECT_NONFINITE is ORed in
   const unsigned char* packed;  // packed model (split-FP16 path) or null
   const float* rx;        // [S][M2]
   float* soft;            // [S][K][2] or null
@@ -79,6 +80,7 @@ struct DetJob {
   const unsigned char* packed;  // packed model (split-FP16 path)
   const float* w;         // [K][M2]
   const int32_t* state;   // [4]
+  int32_t* flags;         // state + 3
   const float* rx;        // [S][M2]
   float* soft;            // [S][K][2] or null
   uint8_t* hard;          // [S][K] or null

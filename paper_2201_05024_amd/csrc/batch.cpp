@@ -61,6 +61,47 @@ int check_item(const apsm_batch_item_t& it, int window) {
                            it.truth, it.err_count);
 }
 
+// Byte ranges [lo, hi) of device buffers.
+struct Range {
+  uintptr_t lo, hi;
+};
+
+void add_range(std::vector<Range>& v, const void* p, size_t bytes) {
+  if (p && bytes) v.push_back({reinterpret_cast<uintptr_t>(p), reinterpret_cast<uintptr_t>(p) + bytes});
+}
+
+// True when no two buffers the batch writes overlap and no buffer it reads
+// overlaps one it writes (the kernels of one launch would race on them).
+bool buffers_disjoint(const std::vector<apsm_batch_item_t>& items) {
+  std::vector<Range> wr, rd;
+  for (const auto& it : items) {
+    const apsm_model_t& m = it.model;
+    const size_t S = it.S > 0 ? (size_t)it.S : 0, K = m.K, cap = m.dict_cap;
+    add_range(wr, m.dict, (size_t)m.M2 * cap * 4);
+    add_range(wr, m.alpha, cap * K * 4);
+    add_range(wr, m.w, K * m.M2 * 4);
+    add_range(wr, m.state, 4 * 4);
+    add_range(wr, m.packed, packed_model_bytes(m.M2, m.K, m.dict_cap));
+    add_range(wr, it.soft, S * K * 2 * 4);
+    add_range(wr, it.hard, S * K);
+    if (S > 0) add_range(wr, it.err_count, K * 8);
+    add_range(rd, it.rx_pilot, (size_t)it.P * m.M2 * 4);
+    add_range(rd, it.sym_pilot, (size_t)it.P * K * 2 * 4);
+    add_range(rd, it.rx, S * m.M2 * 4);
+    add_range(rd, it.truth, S * K);
+  }
+  std::sort(wr.begin(), wr.end(), [](const Range& a, const Range& c) { return a.lo < c.lo; });
+  for (size_t i = 1; i < wr.size(); ++i)
+    if (wr[i].lo < wr[i - 1].hi) return false;
+  for (const Range& r : rd) {
+    // the written range starting last at or before r.hi - 1 is the only one
+    // (of these disjoint ranges) that can reach into r from below or inside
+    auto it = std::upper_bound(wr.begin(), wr.end(), r.hi - 1, [](uintptr_t x, const Range& w) { return x < w.lo; });
+    if (it != wr.begin() && std::prev(it)->hi > r.lo) return false;
+  }
+  return true;
+}
+
 uint64_t fnv(uint64_t h, int64_t v) {
   for (int b = 0; b < 8; ++b) {
     h ^= (uint64_t)((v >> (8 * b)) & 0xff);
@@ -179,6 +220,7 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
     d.packed = static_cast<const unsigned char*>(it.model.packed);
     d.w = it.model.w;
     d.state = it.model.state;
+    d.flags = it.model.state + 3;
     d.rx = it.rx;
     d.soft = it.soft;
     d.hard = it.hard;
@@ -246,6 +288,7 @@ int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* item
   if (int rc = check_params(&pc)) return rc;
   for (int i = 0; i < n; ++i)
     if (int rc = check_item(items[i], params->window)) return rc;
+  if (!buffers_disjoint(std::vector<apsm_batch_item_t>(items, items + n))) return APSM_ERR_INVALID_ARG;
   apsm_batch* b = new (std::nothrow) apsm_batch();
   if (!b) return APSM_ERR_INVALID_ARG;
   b->items.assign(items, items + n);
@@ -261,8 +304,8 @@ int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* item
 size_t apsm_batch_workspace_bytes(const apsm_batch_t* b) { return b ? b->bytes : 0; }
 
 int apsm_batch_bind(apsm_batch_t* b, void* workspace, size_t bytes, void* stream) {
-  if (!b || !workspace) return APSM_ERR_INVALID_ARG;
-  if (bytes < b->bytes || (reinterpret_cast<uintptr_t>(workspace) & 255)) return APSM_ERR_INVALID_ARG;
+  if (!b) return APSM_ERR_INVALID_ARG;
+  if (!workspace || bytes < b->bytes || (reinterpret_cast<uintptr_t>(workspace) & 255)) return APSM_ERR_WORKSPACE;
   // the tables (the kernel rows after them are written on the device)
   std::vector<unsigned char> img(b->off_rows, 0);
   if (!b->tjobs.empty()) std::memcpy(img.data() + b->off_t, b->tjobs.data(), b->tjobs.size() * sizeof(TrainJob));
@@ -370,5 +413,10 @@ int apsm_batch_tune(apsm_batch_t* b, void* stream) {
 }
 
 void apsm_batch_destroy(apsm_batch_t* b) { delete b; }
+
+void apsm_shutdown(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tuned.clear();
+}
 
 }  // extern "C"

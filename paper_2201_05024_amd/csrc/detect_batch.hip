@@ -47,6 +47,7 @@ __device__ __forceinline__ DetJob load_job(const DetJob* p) {
   d.packed = uni(p->packed);
   d.w = uni(p->w);
   d.state = uni(p->state);
+  d.flags = uni(p->flags);
   d.rx = uni(p->rx);
   d.soft = uni(p->soft);
   d.hard = uni(p->hard);

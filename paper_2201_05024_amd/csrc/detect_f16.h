@@ -189,6 +189,7 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
   const float* x = a.rx + (size_t)(my_valid ? my_smp : 0) * M2;
   float xv[M2P / 2];
   float nrm = 0.0f, mx = 0.0f;
+  bool bad = false;                        // a non-finite input component or output
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -198,6 +199,7 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
       src = src < M2 ? src : M2 - 1;
       const float sg = (my_valid && m < M2) ? ((my_part == 1 && m >= M) ? -1.0f : 1.0f) : 0.0f;
       const float t = sg * x[src];
+      bad |= my_valid && m < M2 && !__builtin_isfinite(t);
       xv[8 * b + v] = t;
       nrm = fmaf(t, t, nrm);
       mx = fmaxf(mx, fabsf(t));
@@ -370,6 +372,7 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
     const int k = k0 + u;
     const bool kval = k < K;
     const float val = v[u] + lin[u];
+    bad |= valid && kval && !__builtin_isfinite(val);
     if (a.soft && valid && kval) a.soft[((size_t)smp * a.K + k) * 2 + part] = val;
     if (a.modulation) {
       int idx;
@@ -388,6 +391,7 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
       }
     }
   }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(a.flags, APSM_FLAG_DETECT_NONFINITE);
   if (has_err) {
     __syncthreads();
     if (tid < K && werr[tid]) atomicAdd(a.err + tid, (unsigned long long)werr[tid]);

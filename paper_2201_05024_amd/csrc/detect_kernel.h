@@ -125,6 +125,7 @@ __global__ __launch_bounds__(kThreads, min_waves<M2P>()) void detect_kernel(Dete
   const int part = j & 1;
   float b[NT][KH];
   int smp[NT];
+  bool bad = false;                                   // a non-finite input component or output
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     smp[nt] = smp_base + nt * 16 + (j >> 1);
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(kThreads, min_waves<M2P>()) void detect_kernel(Dete
       src = src < M2 ? src : M2 - 1;
       const float sgn = (valid && k < M2) ? ((part == 1 && k >= M) ? -1.0f : 1.0f) : 0.0f;
       const float v = sgn * x[src];
+      bad |= valid && k < M2 && !__builtin_isfinite(v);
       b[nt][s] = v;
       nrm = fmaf(v, v, nrm);
     }
@@ -223,6 +225,7 @@ __global__ __launch_bounds__(kThreads, min_waves<M2P>()) void detect_kernel(Dete
       for (int s = 0; s < KH - 1; ++s) lin = fmaf(wl[k * M2P + 2 * s + h], b[nt][s], lin);
       float v = acc_k[nt][k] + lin;
       v += __shfl_xor(v, 32);
+      bad |= valid && !__builtin_isfinite(v);
       if (a.soft && valid && (k & 1) == h)
         a.soft[((size_t)smp[nt] * a.K + k) * 2 + part] = v;
       if (a.modulation) {
@@ -243,6 +246,7 @@ __global__ __launch_bounds__(kThreads, min_waves<M2P>()) void detect_kernel(Dete
       }
     }
   }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(a.flags, APSM_FLAG_DETECT_NONFINITE);
   if (has_err) {
     __syncthreads();
     if (tid < K && werr[tid]) atomicAdd(a.err + tid, (unsigned long long)werr[tid]);

@@ -398,13 +398,21 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     float nn = 0.0f;
     if constexpr (ROWS) {
     } else if constexpr (SLOTS > 0) {
+      // ||r_n||^2 summed in the same four groups (m mod 4) and order as the
+      // products r_n . d below, so that for the entry r_n itself
+      // 2 r_n.d - ||r_n||^2 - ||d||^2 is exactly 0: kappa_G(r_n, r_n) = 1 and the
+      // Gram diagonal equals the wL ||r_n||^2 + wG of the projection.
+      float n4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int m = 0; m < M2P; ++m) {
         rn[m] = rrow[m];
-        nn = fmaf(rn[m], rn[m], nn);
+        n4[m & 3] = fmaf(rn[m], rn[m], n4[m & 3]);
       }
+      nn = (n4[0] + n4[1]) + (n4[2] + n4[3]);
     } else {
-      for (int m = 0; m < M2; ++m) nn = fmaf(rrow[m], rrow[m], nn);
+      float n4[4] = {0.0f, 0.0f, 0.0f, 0.0f};        // grouped as above
+      for (int m = 0; m < M2; ++m) n4[m & 3] = fmaf(rrow[m], rrow[m], n4[m & 3]);
+      nn = (n4[0] + n4[1]) + (n4[2] + n4[3]);
     }
     const bool evicting = n >= cap;
     const int L = n + 1 < W ? n + 1 : W;    // |J_n|

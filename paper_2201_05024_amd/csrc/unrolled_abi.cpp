@@ -59,10 +59,10 @@ UnrolledArgs layout(const apsm_unrolled_t* u) {
 int prepare(const apsm_unrolled_t* u, const float* theta, const float* rx_pilot, const float* sym_pilot,
             const float* rx_val, const float* sym_val, void* ws, size_t ws_bytes, UnrolledArgs* out) {
   if (!check(u)) return APSM_ERR_INVALID_ARG;
-  if (!theta || !rx_pilot || !sym_pilot || !rx_val || !sym_val || !ws) return APSM_ERR_INVALID_ARG;
-  if (reinterpret_cast<uintptr_t>(ws) & 255) return APSM_ERR_INVALID_ARG;
+  if (!theta || !rx_pilot || !sym_pilot || !rx_val || !sym_val) return APSM_ERR_INVALID_ARG;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return APSM_ERR_WORKSPACE;
   UnrolledArgs a = layout(u);
-  if (ws_bytes < a.inst_bytes * (size_t)a.n) return APSM_ERR_INVALID_ARG;
+  if (ws_bytes < a.inst_bytes * (size_t)a.n) return APSM_ERR_WORKSPACE;
   a.theta = theta;
   a.rx_pilot = rx_pilot;
   a.sym_pilot = sym_pilot;

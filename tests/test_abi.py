@@ -39,8 +39,20 @@ def test_every_declared_symbol_is_exported():
 def test_strerror_and_version():
     L = A.library()
     assert L.apsm_version().decode().count(".") == 2
-    for code in range(0, 6):
+    for code in range(0, 8):
         assert isinstance(L.apsm_strerror(code), bytes) and L.apsm_strerror(code)
+    assert L.apsm_strerror(A.ERR_WORKSPACE) != L.apsm_strerror(99)
+    assert L.apsm_strerror(A.ERR_NONFINITE) != L.apsm_strerror(99)
+    assert L.apsm_strerror(7) == L.apsm_strerror(99)          # not a code
+
+
+@needs_lib
+def test_shutdown_is_callable_any_time():
+    A.shutdown()
+    A.shutdown()
+    # the library still works on the host afterwards
+    L = A.library()
+    assert L.apsm_train(None, 32, 6, 64, 1, 1, None, None) == A.ERR_INVALID_ARG
 
 
 def _model(M2=32, K=6, cap=256, ptr=1, packed=1):
@@ -134,11 +146,27 @@ def test_packed_bytes():
     assert L.apsm_model_pack(None, None) == 1
 
 
+_NEXT = [1 << 20]
+
+
+def _addr(nbytes=1 << 20):
+    """A distinct fake device address for each buffer (never dereferenced:
+    these tests stop before any launch)."""
+    a = _NEXT[0]
+    _NEXT[0] += ((nbytes + (1 << 20) - 1) >> 20 << 20) + (1 << 20)
+    return a
+
+
+def _fresh_model(M2=32, K=6, cap=256, packed=True):
+    return A._CModel(M2, K, cap, 0, _addr(M2 * cap * 4), _addr(cap * K * 4), _addr(K * M2 * 4), _addr(16),
+                     _addr(1 << 22) if packed else None)
+
+
 def _item(**kw):
     it = A._CBatchItem()
-    it.model = kw.pop("model", _model())
-    base = dict(sigma2=0.5, P=64, rx_pilot=1, sym_pilot=1, S=100, modulation=2, rx=1, soft=1, hard=1,
-                truth=1, err_count=1)
+    it.model = kw.pop("model", None) or _fresh_model()
+    base = dict(sigma2=0.5, P=64, rx_pilot=_addr(), sym_pilot=_addr(), S=100, modulation=2, rx=_addr(),
+                soft=_addr(), hard=_addr(), truth=_addr(), err_count=_addr())
     base.update(kw)
     for k, v in base.items():
         setattr(it, k, v)
@@ -151,8 +179,8 @@ def test_batch_create_plans_on_the_host():
     workspace holds the job tables, one work item per 64 received vectors of
     the detectors on the split-FP16 path, and the claim counters."""
     L = A.library()
-    items = (A._CBatchItem * 3)(_item(), _item(model=_model(M2=16, K=2, cap=100), S=65),
-                                _item(model=_model(M2=128, K=16, cap=100, packed=None), S=1000))
+    items = (A._CBatchItem * 3)(_item(), _item(model=_fresh_model(M2=16, K=2, cap=100), S=65),
+                                _item(model=_fresh_model(M2=128, K=16, cap=100, packed=False), S=1000))
     h = ctypes.c_void_p()
     assert L.apsm_batch_create(ctypes.byref(_params()), items, 3, ctypes.byref(h)) == 0
     nbytes = L.apsm_batch_workspace_bytes(h)
@@ -160,9 +188,10 @@ def test_batch_create_plans_on_the_host():
     assert nbytes >= 256 * 5 and nbytes % 256 == 0
     assert L.apsm_batch_train(h, None) == 1          # not bound to a workspace yet
     assert L.apsm_batch_detect(h, None) == 1
-    assert L.apsm_batch_bind(h, None, nbytes, None) == 1
-    assert L.apsm_batch_bind(h, 256, nbytes - 1, None) == 1   # too small
-    assert L.apsm_batch_bind(h, 257, nbytes, None) == 1       # misaligned
+    assert L.apsm_batch_bind(h, None, nbytes, None) == A.ERR_WORKSPACE
+    assert L.apsm_batch_bind(h, 256, nbytes - 1, None) == A.ERR_WORKSPACE   # too small
+    assert L.apsm_batch_bind(h, 257, nbytes, None) == A.ERR_WORKSPACE       # misaligned
+    assert L.apsm_batch_bind(None, 256, nbytes, None) == A.ERR_INVALID_ARG
     L.apsm_batch_destroy(h)
     L.apsm_batch_destroy(None)
 
@@ -170,8 +199,8 @@ def test_batch_create_plans_on_the_host():
 BAD_ITEMS = [
     dict(sigma2=0.0), dict(P=0), dict(rx_pilot=None), dict(S=-1), dict(modulation=3),
     dict(truth=None), dict(soft=None, hard=None, err_count=None, truth=None), dict(rx=None),
-    dict(model=_model(cap=8)),                           # capacity below the window
-    dict(model=_model(packed=None)),                     # packed form required for this shape
+    dict(model=_fresh_model(cap=8)),                     # capacity below the window
+    dict(model=_fresh_model(packed=False)),              # packed form required for this shape
     dict(modulation=0),                                  # decisions asked without a modulation
 ]
 
@@ -184,6 +213,56 @@ def test_batch_create_rejects_bad_items(kw):
     h = ctypes.c_void_p(1234)
     assert L.apsm_batch_create(ctypes.byref(_params()), items, 2, ctypes.byref(h)) != 0
     assert not h.value
+
+
+def _overlapping(kind):
+    """Two items whose buffers overlap in the way `kind` names."""
+    a, b = _item(), _item()
+    if kind == "soft_soft":           # two detectors writing the same outputs
+        b.soft = a.soft
+    elif kind == "soft_into_hard":    # one output running into another of the same item
+        a.hard = a.soft + 100 * 6 * 2 * 4 - 8
+    elif kind == "model_shared":      # two detectors training into one dictionary
+        b.model.dict = a.model.dict + 64
+    elif kind == "err_shared":
+        b.err_count = a.err_count
+    elif kind == "rx_is_output":      # received vectors of one item are another's soft outputs
+        b.rx = a.soft
+    elif kind == "pilots_in_alpha":
+        b.rx_pilot = a.model.alpha + 4
+    return a, b
+
+
+@needs_lib
+@pytest.mark.parametrize("kind", ["soft_soft", "soft_into_hard", "model_shared", "err_shared", "rx_is_output",
+                                  "pilots_in_alpha"])
+def test_batch_create_rejects_overlapping_buffers(kind):
+    L = A.library()
+    items = (A._CBatchItem * 2)(*_overlapping(kind))
+    h = ctypes.c_void_p(1234)
+    assert L.apsm_batch_create(ctypes.byref(_params()), items, 2, ctypes.byref(h)) == A.ERR_INVALID_ARG
+    assert not h.value
+
+
+@needs_lib
+def test_batch_create_accepts_shared_inputs_and_adjacent_outputs():
+    """Buffers that are only read may be shared; written buffers may touch
+    (end of one = start of the next) without overlapping."""
+    L = A.library()
+    a, b = _item(), _item()
+    b.rx, b.truth, b.rx_pilot, b.sym_pilot = a.rx, a.truth, a.rx_pilot, a.sym_pilot
+    b.soft = a.soft + 100 * 6 * 2 * 4                # right after a's soft outputs
+    b.err_count = a.err_count + 6 * 8
+    items = (A._CBatchItem * 2)(a, b)
+    h = ctypes.c_void_p()
+    assert L.apsm_batch_create(ctypes.byref(_params()), items, 2, ctypes.byref(h)) == 0
+    L.apsm_batch_destroy(h)
+    # a detector with nothing to detect writes no outputs: its output pointers may alias
+    c, d = _item(), _item(S=0)
+    d.soft, d.hard, d.err_count = c.soft, c.hard, c.err_count
+    items = (A._CBatchItem * 2)(c, d)
+    assert L.apsm_batch_create(ctypes.byref(_params()), items, 2, ctypes.byref(h)) == 0
+    L.apsm_batch_destroy(h)
 
 
 @needs_lib
@@ -221,8 +300,10 @@ def test_unrolled_workspace_and_validation():
         assert L.apsm_unrolled_workspace_bytes(ctypes.byref(_unr(**bad))) == 0, bad
     args = [1, 1, 1, 1, 1]
     assert L.apsm_unrolled_forward(ctypes.byref(_unr(K=0)), *args, 256, nbytes, 1, None) == 1
-    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 256, nbytes - 1, 1, None) == 1   # too small
-    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 257, nbytes, 1, None) == 1       # misaligned
+    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 256, nbytes - 1, 1, None) == A.ERR_WORKSPACE
+    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 257, nbytes, 1, None) == A.ERR_WORKSPACE
+    assert L.apsm_unrolled_forward(ctypes.byref(u), *args, None, nbytes, 1, None) == A.ERR_WORKSPACE
+    assert L.apsm_unrolled_backward(ctypes.byref(u), *args, 256, nbytes - 1, None, 1, None) == A.ERR_WORKSPACE
     assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 256, nbytes, None, None) == 1    # no loss
     assert L.apsm_unrolled_forward(ctypes.byref(u), None, 1, 1, 1, 1, 256, nbytes, 1, None) == 1
     assert L.apsm_unrolled_backward(ctypes.byref(u), *args, 256, nbytes, None, None, None) == 1

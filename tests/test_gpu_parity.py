@@ -292,3 +292,53 @@ def test_training_and_packing_stay_inside_the_model(M2, K, cap):
         t = getattr(m, name)
         nbytes = t.numel() * t.element_size()
         assert bool((buf[nbytes:] == 0xA5).all()), (name, M2, K, cap)
+
+
+# ------------------------------------------------------------ status flags
+
+@pytest.mark.parametrize("K,M", [(4, 8), (9, 16)])     # split-FP16 path, FP32 path
+def test_detect_flags_nonfinite_inputs(K, M):
+    """Detection ORs FLAG_DETECT_NONFINITE into the model's flags word when a
+    received vector holds a non-finite component, leaves it clear on finite
+    inputs, and still writes every output; training resets the word."""
+    announce(f"non-finite flag K={K} M={M}")
+    inst = synth.make_instance(synth.InstanceSpec(K=K, M=M, P=64, S=300, snr_db=10.0, seed=901 + K))
+    p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=8, dict_cap=128)
+    m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
+    out = A.detect(m, cuda(inst.rx_data), modulation="qpsk")
+    assert m.status()["flags"] == 0
+    rx = inst.rx_data.copy()
+    rx[123, 2] = np.nan
+    out2 = A.detect(m, cuda(rx), modulation="qpsk")
+    st = m.status()
+    assert st["flags"] == A.FLAG_DETECT_NONFINITE, st
+    assert st["size"] == 128 and st["steps"] == 128           # the rest of the state is untouched
+    s1, s2 = out["soft"].cpu().numpy(), out2["soft"].cpu().numpy()
+    assert not np.isfinite(s2[123]).all()
+    keep = np.arange(len(rx)) != 123
+    # other vectors unaffected (a wave's power-of-two input scale may change)
+    np.testing.assert_allclose(s1[keep], s2[keep], rtol=1e-6, atol=1e-6)
+    rx[123, 2] = np.inf
+    A.detect(m, cuda(rx), modulation="qpsk")
+    assert m.status()["flags"] == A.FLAG_DETECT_NONFINITE
+    m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p, model=m)
+    assert m.status()["flags"] == 0
+
+
+def test_batch_detect_flags_nonfinite_inputs():
+    announce("non-finite flag, batched")
+    insts = [synth.make_instance(synth.InstanceSpec(K=3, M=8, P=64, S=200, snr_db=10.0, seed=950 + i))
+             for i in range(3)]
+    p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=8, dict_cap=128)
+    items = []
+    for i, inst in enumerate(insts):
+        rx = inst.rx_data.copy()
+        if i == 1:
+            rx[7, 0] = np.nan
+        items.append(A.BatchItem(model=A.Model(16, 3, 128, DEV, 0.5), rx_pilot=cuda(inst.rx_pilot),
+                                 sym_pilot=cuda(inst.sym_pilot), rx=cuda(rx), modulation="qpsk",
+                                 soft=torch.empty((200, 3, 2), device=DEV)))
+    b = A.Batch(p, items)
+    b.train().detect()
+    torch.cuda.synchronize()
+    assert [it.model.status()["flags"] for it in items] == [0, A.FLAG_DETECT_NONFINITE, 0]
