@@ -333,6 +333,27 @@ int apsm_unrolled_backward(const apsm_unrolled_t* u, const float* theta, const f
                            void* workspace, size_t ws_bytes, const float* upstream, float* grad,
                            void* stream);
 
+/* ---- training without device allocation ------------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Trains one detector exactly as apsm_batch_train trains a
+ * one-item batch (the kernel rows of every pilot step, then training from
+ * them, then packing: bit-identical results), with the job table and the
+ * kernel rows in a static device array of the library instead of a
+ * workspace.  Arguments, validation and results as for apsm_train; the
+ * shape must have dict_cap <= 4096 (else APSM_ERR_UNSUPPORTED) and need at
+ * most APSM_NOALLOC_SCRATCH_BYTES of scratch: about 2P * (dict_cap + window)
+ * * 4 bytes (else APSM_ERR_WORKSPACE).  Allocates nothing (no hipMalloc or
+ * allocating library call); asynchronous on `stream`.  Each GPU holds its
+ * own copy of the array, from the first call on that GPU until the process
+ * ends; every call on one GPU uses the same copy, so calls that overlap in
+ * time on one GPU (different streams, or threads) race: the caller orders
+ * them. */
+#define APSM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int apsm_train_noalloc(const apsm_params_t* params, int M2, int K, int P,
+                       const float* rx_pilot, const float* sym_pilot,
+                       const apsm_model_t* model, void* stream);
+
 /* Synchronous copy of model->state into host_state[4]; waits for all work on
  * the device.  Returns APSM_ERR_NONFINITE (with host_state filled) when the
  * flags word host_state[3] is nonzero, APSM_OK otherwise. */

@@ -12,7 +12,7 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
-__all__ = ["Params", "Model", "train", "train_batched", "detect", "Batch", "BatchItem", "APSMError",
+__all__ = ["Params", "Model", "train", "train_noalloc", "train_batched", "detect", "Batch", "BatchItem", "APSMError",
            "unrolled_loss", "APSMUnrolled", "library", "shutdown", "LIB_PATH", "MOD_NONE", "MOD_QPSK",
            "MOD_QAM16", "ERR_WORKSPACE", "ERR_NONFINITE", "FLAG_TRAIN_NONFINITE", "FLAG_DETECT_NONFINITE"]
 
@@ -122,6 +122,9 @@ def library() -> ctypes.CDLL:
         L.apsm_last_hip_error.restype = ctypes.c_char_p
         L.apsm_version.argtypes = []
         L.apsm_version.restype = ctypes.c_char_p
+        L.apsm_train_noalloc.argtypes = [ctypes.POINTER(_CParams), i32, i32, i32, vp, vp,
+                                         ctypes.POINTER(_CModel), vp]
+        L.apsm_train_noalloc.restype = i32
         L.apsm_shutdown.argtypes = []
         L.apsm_shutdown.restype = None
         _lib = L
@@ -238,6 +241,25 @@ def train(rx_pilot, sym_pilot, params: Params, model: Optional[Model] = None, st
     del keep
     if rc:
         raise APSMError(rc, "apsm_train")
+    return model
+
+
+def train_noalloc(rx_pilot, sym_pilot, params: Params, model: Model, stream=None) -> Model:
+    """apsm_train_noalloc: training of one detector (dict_cap <= 4096) that
+    allocates no device memory; `model` must be allocated by the caller."""
+    torch = _torch()
+    P, M2 = rx_pilot.shape
+    K = sym_pilot.shape[1]
+    _check(rx_pilot, torch.float32, (P, M2), "rx_pilot")
+    _check(sym_pilot, torch.float32, (P, K, 2), "sym_pilot")
+    model.sigma2 = float(params.sigma2)
+    p, keep = params._c()
+    m = model._c()
+    rc = library().apsm_train_noalloc(ctypes.byref(p), M2, K, P, rx_pilot.data_ptr(), sym_pilot.data_ptr(),
+                                      ctypes.byref(m), _stream_handle(stream))
+    del keep
+    if rc:
+        raise APSMError(rc, "apsm_train_noalloc")
     return model
 
 
