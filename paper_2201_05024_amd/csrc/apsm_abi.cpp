@@ -165,7 +165,7 @@ int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const f
   }
   for (int i = 0; i < n_inst; ++i) {
     const apsm_model_t& m = models[i];
-    hipError_t e = apsm::launch_pack_model(m.dict, m.alpha, m.state, m.dict_cap, M2, K, m.packed,
+    hipError_t e = apsm::launch_pack_model(m.dict, m.alpha, m.w, m.state, m.dict_cap, M2, K, m.packed,
                                            (hipStream_t)stream);
     if (e != hipSuccess) return hip_status(e);
   }
@@ -197,7 +197,7 @@ size_t apsm_model_packed_bytes(int M2, int K, int dict_cap) {
 
 int apsm_model_pack(const apsm_model_t* model, void* stream) {
   if (int rc = check_model(model)) return rc;
-  return hip_status(apsm::launch_pack_model(model->dict, model->alpha, model->state, model->dict_cap,
+  return hip_status(apsm::launch_pack_model(model->dict, model->alpha, model->w, model->state, model->dict_cap,
                                             model->M2, model->K, model->packed, (hipStream_t)stream));
 }
 

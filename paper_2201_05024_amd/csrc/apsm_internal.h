@@ -119,23 +119,40 @@ hipError_t launch_kernel_rows(const TrainJob* jobs, const int4* items, int n_ite
 hipError_t launch_train_rows(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
                              hipStream_t stream);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t stream);
-// Packed model for the split-FP16 detection path: bytes (0 when the shape
-// uses the FP32 path) and the packing launch (no-op for such shapes).
+// Packed model of the detection kernels (split-FP16 layout for 2M <= 64 and
+// K <= 8, two-contraction layout otherwise): bytes and the packing launch.
 size_t packed_model_bytes(int M2, int K, int cap);
-hipError_t launch_pack_model(const float* dict, const float* alpha, const int32_t* state, int cap,
+hipError_t launch_pack_model(const float* dict, const float* alpha, const float* w, const int32_t* state, int cap,
                              int M2, int K, void* packed, hipStream_t stream);
 
-// One model to pack in a batched packing launch (shapes of the split-FP16
-// path only); variant = detect_batch_variant(M2, K).
+// One model to pack in a batched packing launch; variant =
+// detect_batch_variant(M2, K) for the split-FP16 (VALU-coefficient) layout,
+// unused for the two-contraction layout.
 struct PackJob {
   const float* dict;
   const float* alpha;
+  const float* w;
   const int32_t* state;
   unsigned char* packed;
   int cap, M2, K, variant;
 };
-// Packs jobs[0..n) (device table), max_cap the largest capacity among them.
+// Packs jobs[0..n) (device table) in the split-FP16 layout, max_cap the
+// largest capacity among them.
 hipError_t launch_pack_model_batch(const PackJob* jobs, int n, int max_cap, hipStream_t stream);
+
+// Two-contraction detection (detect_wide.h): every shape the split-FP16
+// kernels do not hold (2M > 64 or K > 8).  Packing many models in one
+// launch pair (max_threads: the largest wide_pack_threads of the jobs) and
+// detection of many jobs in one launch over (job, item) pairs, item i of a
+// job covering received vectors 128 i .. 128 i + 127 (persistent form with
+// ctr as for launch_detect_batch).
+bool detect_is_wide(int M2, int K);
+int wide_pack_threads(int M2, int cap);
+int wide_detect_variant(int M2);
+int wide_detect_items(int S);
+hipError_t launch_pack_wide_batch(const PackJob* jobs, int n, int max_threads, hipStream_t stream);
+hipError_t launch_detect_wide_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr, int grid,
+                                    hipStream_t stream);
 
 // Batched detection.  Jobs whose shape has detect_batch_variant >= 0 run in
 // one launch over a global sequence of work items, item i being tile

@@ -6,11 +6,13 @@
 // specialisation picked by train_rows_variant, else train_variant), ordered
 // by estimated cost so the longest trainings start first.  Jobs of the rows
 // form get their kernel rows (one step per row) in the workspace, written by
-// one data-parallel launch before the training launch.  Items whose shape the split-FP16 path
-// covers (2M <= 64, K <= 8) become packing jobs and detection jobs; their
-// 64-vector tiles form one global work-item list, ordered by the cost of a
-// tile (dictionary size times per-entry work), most expensive first.  Other
-// items are detected by their own apsm_detect launch after the batched one.
+// one data-parallel launch before the training launch.  Every item becomes a
+// packing job and, if it has vectors to detect, a detection job of one of the
+// two detection kernels: split-FP16 with VALU coefficients (2M <= 64, K <= 8)
+// or two-contraction (wider shapes).  Each kernel gets one launch over the
+// work items of its jobs (64-vector tiles, resp. 256-vector items), ordered
+// by the cost of an item (dictionary size times per-entry work), most
+// expensive first.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -34,14 +36,18 @@ struct apsm_batch {
   int rows_max_m2 = 0;
   std::vector<apsm::PackJob> pjobs;
   int pack_max_cap = 0;
+  std::vector<apsm::PackJob> pwjobs;           // two-contraction packing
+  int pack_wide_threads = 0;
   std::vector<apsm::DetJob> djobs;
   std::vector<int2> ditems;
-  std::vector<int> plain;            // items detected with their own launch
+  std::vector<apsm::DetJob> wjobs;             // two-contraction detection
+  std::vector<int2> witems;
   std::vector<int> train_plain;      // items trained with their own launch
-  size_t off_t = 0, off_rj = 0, off_ri = 0, off_p = 0, off_d = 0, off_i = 0, off_c = 0, off_rows = 0, bytes = 0;
+  size_t off_t = 0, off_rj = 0, off_ri = 0, off_p = 0, off_pw = 0, off_d = 0, off_i = 0, off_wd = 0, off_wi = 0,
+         off_c = 0, off_rows = 0, bytes = 0;
   unsigned char* ws = nullptr;       // bound workspace (device)
   bool persistent = true;
-  int grid = 0;
+  int grid = 0, grid_wide = 0;
   uint64_t signature = 0;
 };
 
@@ -186,36 +192,45 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
   }
 
   // packing and detection
-  std::vector<int> det;
+  std::vector<int> det, wdet;
   for (int i = 0; i < n; ++i) {
     const auto& it = b.items[i];
-    const int v = detect_batch_variant(it.model.M2, it.model.K);
-    if (v < 0) {
-      if (it.S > 0) b.plain.push_back(i);
-      continue;
-    }
+    const bool wide = detect_is_wide(it.model.M2, it.model.K);
     PackJob pj{};
     pj.dict = it.model.dict;
     pj.alpha = it.model.alpha;
+    pj.w = it.model.w;
     pj.state = it.model.state;
     pj.packed = static_cast<unsigned char*>(it.model.packed);
     pj.cap = it.model.dict_cap;
     pj.M2 = it.model.M2;
     pj.K = it.model.K;
-    pj.variant = v;
-    b.pjobs.push_back(pj);
-    b.pack_max_cap = std::max(b.pack_max_cap, pj.cap);
-    if (it.S > 0) det.push_back(i);
+    pj.variant = wide ? -1 : detect_batch_variant(it.model.M2, it.model.K);
+    if (wide) {
+      b.pwjobs.push_back(pj);
+      b.pack_wide_threads = std::max(b.pack_wide_threads, wide_pack_threads(pj.M2, pj.cap));
+    } else {
+      b.pjobs.push_back(pj);
+      b.pack_max_cap = std::max(b.pack_max_cap, pj.cap);
+    }
+    if (it.S > 0) (wide ? wdet : det).push_back(i);
   }
+  // cost of one work item: dictionary stages times per-entry work
   std::vector<double> dcost(n, 0.0);
   for (int i : det) {
     const auto& it = b.items[i];
     const double D = std::min<double>(2.0 * it.P, it.model.dict_cap);
     dcost[i] = (std::ceil(D / 64.0) + 0.25) * (it.model.K + 6 + it.model.M2 / 16.0);
   }
-  std::stable_sort(det.begin(), det.end(), [&](int a, int c) { return dcost[a] > dcost[c]; });
-  for (int i : det) {
+  for (int i : wdet) {
     const auto& it = b.items[i];
+    const double D = std::min<double>(2.0 * it.P, it.model.dict_cap);
+    dcost[i] = (std::ceil(D / 64.0) + 0.25) * (6.0 * it.model.M2 / 32.0 + 1.0);
+  }
+  auto by_cost = [&](int a, int c) { return dcost[a] > dcost[c]; };
+  std::stable_sort(det.begin(), det.end(), by_cost);
+  std::stable_sort(wdet.begin(), wdet.end(), by_cost);
+  auto det_job = [&](const apsm_batch_item_t& it, int variant) {
     DetJob d{};
     d.packed = static_cast<const unsigned char*>(it.model.packed);
     d.w = it.model.w;
@@ -232,20 +247,34 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
     d.S = it.S;
     d.modulation = it.modulation;
     d.c2 = kLog2e / (2.0f * it.sigma2);
-    d.variant = detect_batch_variant(d.M2, d.K);
+    d.variant = variant;
+    return d;
+  };
+  for (int i : det) {
+    const auto& it = b.items[i];
     const int job = (int)b.djobs.size();
-    b.djobs.push_back(d);
+    b.djobs.push_back(det_job(it, detect_batch_variant(it.model.M2, it.model.K)));
     const int tiles = detect_tiles(it.S);
     for (int t = 0; t < tiles; ++t) b.ditems.push_back(make_int2(job, t));
+  }
+  for (int i : wdet) {
+    const auto& it = b.items[i];
+    const int job = (int)b.wjobs.size();
+    b.wjobs.push_back(det_job(it, wide_detect_variant(it.model.M2)));
+    const int nit = wide_detect_items(it.S);
+    for (int t = 0; t < nit; ++t) b.witems.push_back(make_int2(job, t));
   }
 
   b.off_t = 0;
   b.off_rj = align256(b.off_t + b.tjobs.size() * sizeof(TrainJob));
   b.off_ri = align256(b.off_rj + b.rjobs.size() * sizeof(TrainJob));
   b.off_p = align256(b.off_ri + b.ritems.size() * sizeof(int4));
-  b.off_d = align256(b.off_p + b.pjobs.size() * sizeof(PackJob));
+  b.off_pw = align256(b.off_p + b.pjobs.size() * sizeof(PackJob));
+  b.off_d = align256(b.off_pw + b.pwjobs.size() * sizeof(PackJob));
   b.off_i = align256(b.off_d + b.djobs.size() * sizeof(DetJob));
-  b.off_c = align256(b.off_i + b.ditems.size() * sizeof(int2));
+  b.off_wd = align256(b.off_i + b.ditems.size() * sizeof(int2));
+  b.off_wi = align256(b.off_wd + b.wjobs.size() * sizeof(DetJob));
+  b.off_c = align256(b.off_wi + b.witems.size() * sizeof(int2));
   b.off_rows = b.off_c + 256;                 // tables end here (the bound image)
   b.bytes = b.off_rows + b.rows_floats * sizeof(float);
   b.signature = signature_of(b.items);
@@ -258,18 +287,18 @@ const T* at(const apsm_batch* b, size_t off) {
   return reinterpret_cast<const T*>(b->ws + off);
 }
 
+// The two detection launches; the persistent forms use the counter pairs at
+// off_c (split-FP16) and off_c + 8 (two-contraction).
 int run_detect(const apsm_batch* b, bool persistent, hipStream_t stream) {
-  if (!b->ditems.empty()) {
-    unsigned int* ctr = persistent ? reinterpret_cast<unsigned int*>(b->ws + b->off_c) : nullptr;
-    hipError_t e = launch_detect_batch(at<DetJob>(b, b->off_d), at<int2>(b, b->off_i), (int)b->ditems.size(), ctr,
-                                       b->grid, stream);
+  unsigned int* ctr = reinterpret_cast<unsigned int*>(b->ws + b->off_c);
+  if (!b->witems.empty()) {
+    hipError_t e = launch_detect_wide_batch(at<DetJob>(b, b->off_wd), at<int2>(b, b->off_wi), (int)b->witems.size(),
+                                            persistent ? ctr + 2 : nullptr, b->grid_wide, stream);
     if (e != hipSuccess) return hip_status(e);
   }
-  for (int i : b->plain) {
-    const auto& it = b->items[i];
-    const DetectArgs a = detect_args(&it.model, it.sigma2, it.S, it.rx, it.soft, it.hard, it.modulation,
-                                     it.truth, it.err_count);
-    hipError_t e = launch_detect(a, stream);
+  if (!b->ditems.empty()) {
+    hipError_t e = launch_detect_batch(at<DetJob>(b, b->off_d), at<int2>(b, b->off_i), (int)b->ditems.size(),
+                                       persistent ? ctr : nullptr, b->grid, stream);
     if (e != hipSuccess) return hip_status(e);
   }
   return APSM_OK;
@@ -293,7 +322,7 @@ int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* item
   if (!b) return APSM_ERR_INVALID_ARG;
   b->items.assign(items, items + n);
   plan(*b, &pc);
-  if (b->ditems.size() > (size_t)INT32_MAX) {
+  if (b->ditems.size() > (size_t)INT32_MAX || b->witems.size() > (size_t)INT32_MAX) {
     delete b;
     return APSM_ERR_UNSUPPORTED;
   }
@@ -320,14 +349,18 @@ int apsm_batch_bind(apsm_batch_t* b, void* workspace, size_t bytes, void* stream
   }
   if (!b->ritems.empty()) std::memcpy(img.data() + b->off_ri, b->ritems.data(), b->ritems.size() * sizeof(int4));
   if (!b->pjobs.empty()) std::memcpy(img.data() + b->off_p, b->pjobs.data(), b->pjobs.size() * sizeof(PackJob));
+  if (!b->pwjobs.empty()) std::memcpy(img.data() + b->off_pw, b->pwjobs.data(), b->pwjobs.size() * sizeof(PackJob));
   if (!b->djobs.empty()) std::memcpy(img.data() + b->off_d, b->djobs.data(), b->djobs.size() * sizeof(DetJob));
   if (!b->ditems.empty()) std::memcpy(img.data() + b->off_i, b->ditems.data(), b->ditems.size() * sizeof(int2));
+  if (!b->wjobs.empty()) std::memcpy(img.data() + b->off_wd, b->wjobs.data(), b->wjobs.size() * sizeof(DetJob));
+  if (!b->witems.empty()) std::memcpy(img.data() + b->off_wi, b->witems.data(), b->witems.size() * sizeof(int2));
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(workspace, img.data(), img.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_status(e);
   b->ws = static_cast<unsigned char*>(workspace);
   b->grid = detect_batch_grid();
+  b->grid_wide = b->grid / 2;        // one 512-thread workgroup per CU
   return APSM_OK;
 }
 
@@ -347,9 +380,9 @@ int apsm_batch_train_prepared(const apsm_batch_t* b, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_train_rows(at<TrainJob>(b, b->off_rj), (int)b->rjobs.size(), b->cm, b->rows_lds, s);
   if (e == hipSuccess) e = launch_train_table(at<TrainJob>(b, b->off_t), (int)b->tjobs.size(), b->cm, b->train_lds, s);
-  if (e == hipSuccess) e = launch_pack_model_batch(at<PackJob>(b, b->off_p), (int)b->pjobs.size(), b->pack_max_cap, s);
   for (size_t q = 0; q < b->train_plain.size() && e == hipSuccess; ++q) {
-    // shapes outside the table kernel (2M > 64): one launch each, no packed form
+    // shapes outside the table kernel (2M > 64, dictionaries past the rows
+    // form): one launch each
     const auto& it = b->items[b->train_plain[q]];
     TrainArgs a{};
     a.cm = b->cm;
@@ -367,6 +400,10 @@ int apsm_batch_train_prepared(const apsm_batch_t* b, void* stream) {
     a.c2 = kLog2e / (2.0f * it.sigma2);
     e = launch_train(a, s);
   }
+  // packing reads the trained models: after every training launch
+  if (e == hipSuccess) e = launch_pack_model_batch(at<PackJob>(b, b->off_p), (int)b->pjobs.size(), b->pack_max_cap, s);
+  if (e == hipSuccess)
+    e = launch_pack_wide_batch(at<PackJob>(b, b->off_pw), (int)b->pwjobs.size(), b->pack_wide_threads, s);
   return hip_status(e);
 }
 
@@ -378,7 +415,7 @@ int apsm_batch_detect(const apsm_batch_t* b, void* stream) {
 int apsm_batch_tune(apsm_batch_t* b, void* stream) {
   if (!b || !b->ws) return APSM_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  if (b->ditems.empty()) return APSM_OK;
+  if (b->ditems.empty() && b->witems.empty()) return APSM_OK;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError());
   if (hipEventCreate(&e1) != hipSuccess) {

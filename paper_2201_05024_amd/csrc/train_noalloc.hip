@@ -115,7 +115,7 @@ int apsm_train_noalloc(const apsm_params_t* p, int M2, int K, int P, const float
   if (e == hipSuccess) e = launch_kernel_rows(job, items, (int)n_items, M2, cm, s);
   if (e == hipSuccess) e = launch_train_rows(job, 1, cm, train_rows_lds_bytes(W, M2, K), s);
   if (e == hipSuccess)
-    e = launch_pack_model(model->dict, model->alpha, model->state, cap, M2, K, model->packed, s);
+    e = launch_pack_model(model->dict, model->alpha, model->w, model->state, cap, M2, K, model->packed, s);
   return hip_status(e);
 }
 

@@ -189,3 +189,80 @@ def spec_batch_mixed(i: int, seed: int = BASE_SEED + 3, S: int = 1 << 16):
     snr = float(rng.uniform(5.0, 20.0))
     spec = InstanceSpec(K=K, M=M, P=D, S=S, snr_db=snr, modulation=mod, seed=seed * 1000 + i)
     return spec, D
+
+
+LARGE_INSTANCES = 16
+
+
+def spec_large(i: int = 0, seed: int = BASE_SEED + 5, S: int = 1 << 22, P: int = 8192) -> InstanceSpec:
+    """Instance i of the large-array workload: 16 users with 16-QAM, 64
+    receive antennas (2M = 128), Rapp PA at every transmitter, 20 dB, 8192
+    pilots (2P = 16384 real training vectors, twice the dictionary capacity
+    8192) and 4,194,304 data symbols."""
+    return InstanceSpec(K=16, M=64, P=P, S=S, snr_db=20.0, modulation="qam16", rapp=(2.0, 1.0),
+                        seed=seed * 1000 + i)
+
+
+@dataclass
+class DeviceInstance:
+    """An instance whose data block lives in device memory (torch tensors);
+    pilots and channel are host arrays as in Instance."""
+    spec: InstanceSpec
+    rx_pilot: np.ndarray        # [P][2M] float32 (host)
+    sym_pilot: np.ndarray       # [P][K][2] float32 (host)
+    rx_data: object             # [S][2M] float32 torch tensor on the device
+    truth: object               # [S][K] uint8 torch tensor on the device
+    scale: float
+    extras: dict = field(default_factory=dict)
+
+
+def make_instance_device(spec: InstanceSpec, device) -> DeviceInstance:
+    """The recipe of make_instance for data blocks too large to draw on the
+    host.  The channel, the user powers and the pilot block come from
+    PCG64(spec.seed) in make_instance's order (so they equal make_instance's);
+    the data block is drawn on `device` by torch's Philox generator seeded
+    with spec.seed: symbol indices uniform over the constellation levels,
+    the same Rapp PA, powers, channel and noise level, and the pilots' scale.
+    The same spec and device type give the same arrays."""
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    K, M = spec.K, spec.M
+    H = (rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))) / np.sqrt(2.0)
+    if spec.near_far_db is not None:
+        lo, hi = spec.near_far_db
+        p = 10.0 ** (rng.uniform(lo, hi, size=K) / 10.0)
+    else:
+        p = np.ones(K)
+    n0 = 10.0 ** (-spec.snr_db / 10.0)
+    b_p, _ = _draw_symbols(rng, spec.P, K, spec.modulation)
+    x_p = _rapp(b_p, *spec.rapp) if spec.rapp is not None else b_p
+    noise = (rng.standard_normal((spec.P, M)) + 1j * rng.standard_normal((spec.P, M))) * np.sqrt(n0 / 2.0)
+    r_p = (x_p * np.sqrt(p)[None, :]) @ H.T + noise
+    scale = 1.0 / np.sqrt(np.mean(np.sum(np.abs(r_p) ** 2, axis=1)))
+    r_p = r_p * scale
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(spec.seed))
+    S = spec.S
+    lv = torch.tensor(_LEVELS[spec.modulation], dtype=torch.float32, device=device)
+    idx = torch.randint(0, len(_LEVELS[spec.modulation]), (S, K, 2), generator=g, device=device)
+    b = torch.complex(lv[idx[..., 0]], lv[idx[..., 1]])
+    if spec.rapp is not None:
+        pr, a_sat = spec.rapp
+        b = b * (1.0 + (b.abs() / a_sat) ** (2.0 * pr)) ** (-1.0 / (2.0 * pr))
+    amp = torch.tensor(np.sqrt(p), dtype=torch.float32, device=device)
+    Ht = torch.tensor(H.T.copy(), dtype=torch.complex64, device=device).contiguous()   # [K][M]
+    r = (b * amp[None, :]) @ Ht
+    del b
+    nz = torch.randn((S, M, 2), generator=g, device=device) * float(np.sqrt(n0 / 2.0))
+    r = (r + torch.complex(nz[..., 0], nz[..., 1])) * float(scale)
+    del nz
+    rx = torch.cat([r.real, r.imag], dim=-1).contiguous()
+    del r
+    bits = BITS_PER_AXIS[spec.modulation]
+    gray_t = idx ^ (idx >> 1)
+    truth = ((gray_t[..., 0] << bits) | gray_t[..., 1]).to(torch.uint8)
+    sym_p = np.stack([b_p.real, b_p.imag], axis=-1).astype(np.float32)
+    return DeviceInstance(spec=spec, rx_pilot=_to_planar(r_p), sym_pilot=sym_p, rx_data=rx, truth=truth,
+                          scale=float(scale), extras={"H": H, "p": p})

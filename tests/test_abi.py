@@ -123,8 +123,8 @@ def test_detect_rejects_bad_args():
     assert call(rx=None) == 1
     assert call(model=_model(M2=7)) == 2
     assert call(model=_model(K=0)) == 2
-    assert call(model=_model(packed=None)) == 1         # this shape needs the packed form
-    assert call(model=_model(M2=128, K=6, packed=None), S=0) == 0   # ... this one does not
+    assert call(model=_model(packed=None)) == 1         # every shape needs the packed form
+    assert call(model=_model(M2=128, K=6, packed=None), S=0) == 1
     assert call(S=0) == 0                               # empty input: nothing launched
     assert call(S=0, rx=None, soft=None) == 0           # ... and no buffers needed
 
@@ -135,7 +135,14 @@ def test_packed_bytes():
     L.apsm_model_packed_bytes.restype = ctypes.c_size_t
     # 2M = 32 -> rows of (2*32 + 8) halves, K = 6 -> (8 + 4) floats per entry, cap 1000 -> 1024 rows
     assert L.apsm_model_packed_bytes(32, 6, 1000) == 64 + 1024 * (72 * 2 + 12 * 4)
-    assert L.apsm_model_packed_bytes(128, 16, 1000) == 0      # detected without a packed form
+    # two-contraction layout (2M > 64 or K > 8): 256-byte header, the linear
+    # weights (2M/32 x 2 KiB), stages of 64 entries: rows of (2 * 2M + 8)
+    # halves, 4 KiB of coefficients, 1 KiB of norms
+    assert L.apsm_model_packed_bytes(128, 16, 1000) == 256 + 4 * 2048 + 16 * (64 * 528 + 4096 + 1024)
+    assert L.apsm_model_packed_bytes(128, 3, 64) == 256 + 4 * 2048 + 1 * (64 * 528 + 4096 + 1024)
+    assert L.apsm_model_packed_bytes(32, 9, 65) == 256 + 1 * 2048 + 2 * (64 * 144 + 4096 + 1024)
+    assert L.apsm_model_packed_bytes(20, 12, 10) == L.apsm_model_packed_bytes(32, 16, 64)
+    assert L.apsm_model_packed_bytes(66, 1, 10) == L.apsm_model_packed_bytes(128, 16, 64)
     # 2M = 40 runs with the 64-wide layout: rows of 2*64+8 halves, K4 + 4 floats each
     assert L.apsm_model_packed_bytes(40, 2, 40) == 64 + 128 * ((2 * 64 + 8) * 2 + (4 + 4) * 4)
     for m2 in range(34, 65, 2):
@@ -180,7 +187,7 @@ def test_batch_create_plans_on_the_host():
     the detectors on the split-FP16 path, and the claim counters."""
     L = A.library()
     items = (A._CBatchItem * 3)(_item(), _item(model=_fresh_model(M2=16, K=2, cap=100), S=65),
-                                _item(model=_fresh_model(M2=128, K=16, cap=100, packed=False), S=1000))
+                                _item(model=_fresh_model(M2=128, K=16, cap=100), S=1000))
     h = ctypes.c_void_p()
     assert L.apsm_batch_create(ctypes.byref(_params()), items, 3, ctypes.byref(h)) == 0
     nbytes = L.apsm_batch_workspace_bytes(h)

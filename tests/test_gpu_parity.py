@@ -50,6 +50,13 @@ DETECT_CASES = [
     (9, 16, 100, 77, 200, 16, "qpsk"),      # K > 8: one column tile per wave
     (16, 64, 64, 300, 100, 8, "qam16"),     # M2 = 128
     (6, 32, 40, 129, 80, 32, "qpsk"),       # M2 = 64
+    # two-contraction kernel (2M > 64 or K > 8): every padded width, ragged
+    # widths, users 1..16, several stages and a ragged last stage
+    (12, 24, 200, 500, 300, 16, "qam16"),   # M2 = 48 -> 64, K = 12
+    (10, 50, 150, 333, 260, 8, "qpsk"),     # M2 = 100 -> 128
+    (16, 64, 300, 1000, 600, 32, "qam16"),  # M2 = 128, K = 16, 10 stages
+    (1, 40, 60, 97, 100, 8, "qpsk"),        # M2 = 80, K = 1
+    (9, 2, 50, 70, 64, 8, "qam16"),         # M2 = 4 -> 32, K = 9, D = 64 (one full stage)
 ]
 
 
@@ -342,3 +349,56 @@ def test_batch_detect_flags_nonfinite_inputs():
     b.train().detect()
     torch.cuda.synchronize()
     assert [it.model.status()["flags"] for it in items] == [0, A.FLAG_DETECT_NONFINITE, 0]
+
+
+
+# ------------------------------------------------------------ large array
+
+def test_detect_large_array_full_size_sampled():
+    """The large-array shape at full size: 16 users (16-QAM), 2M = 128, a full
+    dictionary of 8192 entries, 4,194,304 received vectors in one launch.  The
+    dictionary is the last 8192 real training vectors of the pilots (what a
+    capacity-8192 training leaves), the coefficients and linear weights are
+    seeded draws (training at this size is covered elsewhere).  Outputs of a
+    spread sample (the first and last 32 vectors and every 16384th) are
+    checked against the FP64 oracle; on all vectors the decisions must be the
+    slicer of the soft outputs, the error counts must equal the mismatches
+    with the truth, and no non-finite flag may be raised."""
+    announce("large array: K=16 2M=128 D=8192 S=4194304")
+    spec = synth.spec_large(0)
+    inst = synth.make_instance_device(spec, DEV)
+    K, M2, cap = spec.K, 2 * spec.M, 8192
+    rx_c = synth.planar_to_complex(inst.rx_pilot)
+    sym_c = synth.pair_to_complex(inst.sym_pilot)
+    R, _ = O.training_sequence(rx_c, sym_c)
+    d = R[-cap:].astype(np.float32)                      # slot n % cap of sample n = 8192 + s
+    rng = np.random.default_rng(55)
+    alpha = (rng.standard_normal((cap, K)) * 0.05).astype(np.float32)
+    w = (rng.standard_normal((K, M2)) * 0.05).astype(np.float32)
+    m = A.Model(M2, K, cap, DEV, 0.5)
+    m.dict.copy_(cuda(d.T))
+    m.alpha.copy_(cuda(alpha))
+    m.w.copy_(cuda(w))
+    m.state.copy_(cuda(np.array([cap, 0, 2 * spec.P, 0], dtype=np.int32)))
+    m.pack()
+    out = A.detect(m, inst.rx_data, modulation="qam16", truth=inst.truth)
+    torch.cuda.synchronize()
+    S = spec.S
+    idx = np.unique(np.r_[0:32, np.arange(0, S, 16384), S - 32:S])
+    rx_sub = inst.rx_data[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    f = ring_to_oracle_model(d.astype(np.float64), alpha.astype(np.float64), w.astype(np.float64), 0.5, cap)
+    soft_ref = O.detect_planar(f, rx_sub, chunk=8)
+    soft = out["soft"].cpu().numpy()
+    worst, _ = compare_soft(soft[idx], soft_ref, "qam16")
+    assert worst <= REL_TOL, worst
+    hard = out["hard"].cpu().numpy()
+    outside, inside = compare_hard(hard[idx], soft_ref, "qam16")
+    assert outside == 0, (outside, inside)
+    # decisions are the slicer of the soft outputs (values within 1e-6 of a
+    # threshold excepted: the kernel compares against FP32 thresholds)
+    s64 = soft.astype(np.float64)
+    mism = (hard != O.decide(s64, "qam16")) & (O.boundary_distance(s64, "qam16") >= 1e-6)
+    assert not mism.any(), int(mism.sum())
+    truth = inst.truth.cpu().numpy()
+    np.testing.assert_array_equal(out["errors"].cpu().numpy(), O.symbol_errors(hard, truth))
+    assert m.status()["flags"] == 0

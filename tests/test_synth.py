@@ -43,3 +43,26 @@ def test_rapp_qpsk_gain():
     b = np.array([1 + 0j, (1 + 1j) / math.sqrt(2)])
     x = synth._rapp(b, 2.0, 1.0)
     assert np.allclose(np.abs(x), 2 ** -0.25)
+
+
+def test_device_generator_follows_the_host_recipe():
+    """make_instance_device: pilots and channel equal make_instance's; the data
+    block (drawn by torch) has the recipe's statistics and label alphabet and
+    is reproducible from the seed."""
+    torch = __import__("pytest").importorskip("torch")
+    spec = synth.spec_large(3, S=4000, P=300)
+    host = synth.make_instance(spec)
+    dev = synth.make_instance_device(spec, "cpu")
+    np.testing.assert_array_equal(dev.rx_pilot, host.rx_pilot)
+    np.testing.assert_array_equal(dev.sym_pilot, host.sym_pilot)
+    assert dev.scale == host.scale
+    assert dev.rx_data.shape == (4000, 128) and dev.rx_data.dtype == torch.float32
+    assert dev.truth.shape == (4000, 16) and int(dev.truth.max()) <= 15
+    # unit mean squared norm over the pilots; the data block shares the scale
+    m = float((dev.rx_data.double() ** 2).sum(1).mean())
+    assert abs(m - 1.0) < 0.03, m
+    again = synth.make_instance_device(spec, "cpu")
+    assert torch.equal(again.rx_data, dev.rx_data) and torch.equal(again.truth, dev.truth)
+    # every one of the 16 labels occurs, about equally often
+    counts = np.bincount(dev.truth.numpy().ravel(), minlength=16)
+    assert counts.min() > 0.8 * counts.mean()
