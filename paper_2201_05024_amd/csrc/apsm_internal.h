@@ -31,7 +31,8 @@ struct TrainJob {
   float* alpha;           // [cap][K]
   float* w;               // [K][M2]
   int32_t* state;         // [4]
-  int P, M2, K, cap;
+  int P, M2, K, cap;      // K: users this job trains (k0 .. k0 + K - 1)
+  int Kt, k0;             // the detector's users (row stride of sym and alpha), first user of the job
   float c2;               // log2e / (2 sigma^2)
   int variant;            // kernel specialisation (train_variant), table launches only
   // Precomputed kernel rows (rows launches only, else null): for step n,
@@ -111,6 +112,10 @@ hipError_t launch_train_table(const TrainJob* jobs, int n, const TrainCommon& cm
 // the jobs), then launch_train_rows trains, workgroup b running jobs[b] with
 // the variant train_rows_variant set.
 int train_rows_variant(int M2, int K, int cap);   // -1 if the shape is not covered
+// Users one rows job may train for this capacity (16, or 4 when the
+// coefficients of dict_cap > 4096 slots need 16 register slots per thread):
+// detectors with more users train as several jobs of consecutive users.
+int train_rows_max_users(int cap);
 size_t train_rows_lds_bytes(int W, int M2, int K);
 int kernel_rows_tile_steps();
 int kernel_rows_tile_lags();

@@ -157,7 +157,10 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tcost[a] > tcost[c]; });
   for (int i : order) {
     const auto& it = b.items[i];
-    const int rv = train_rows_variant(it.model.M2, it.model.K, it.model.dict_cap);
+    // users per rows job: all of them, or groups of four when the capacity
+    // needs 16 coefficient slots per thread
+    const int ku = std::min(it.model.K, train_rows_max_users(it.model.dict_cap));
+    const int rv = train_rows_variant(it.model.M2, ku, it.model.dict_cap);
     if (rv < 0 && !train_in_table(it.model.M2)) {
       b.train_plain.push_back(i);
       continue;
@@ -172,15 +175,24 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
     j.P = it.P;
     j.M2 = it.model.M2;
     j.K = it.model.K;
+    j.Kt = it.model.K;
+    j.k0 = 0;
     j.cap = it.model.dict_cap;
     j.c2 = kLog2e / (2.0f * it.sigma2);
     if (rv >= 0) {
+      // one job per group of ku users, all reading the detector's kernel rows;
+      // the rows tiles name the first group's job
       const int q = (int)b.rjobs.size(), T = 2 * it.P;
-      j.variant = rv;
-      b.rjobs.push_back(j);
-      b.rows_off.push_back(b.rows_floats);
+      for (int k0 = 0; k0 < it.model.K; k0 += ku) {
+        TrainJob g = j;
+        g.k0 = k0;
+        g.K = std::min(ku, it.model.K - k0);
+        g.variant = train_rows_variant(g.M2, g.K, g.cap);
+        b.rjobs.push_back(g);
+        b.rows_off.push_back(b.rows_floats);
+        b.rows_lds = std::max(b.rows_lds, train_rows_lds_bytes(p->window, g.M2, g.K));
+      }
       b.rows_floats += (size_t)T * (j.cap + p->window);
-      b.rows_lds = std::max(b.rows_lds, train_rows_lds_bytes(p->window, j.M2, j.K));
       b.rows_max_m2 = std::max(b.rows_max_m2, j.M2);
       for (int n0 = 0; n0 < T; n0 += kernel_rows_tile_steps())
         for (int l0 = 0; l0 < j.cap; l0 += kernel_rows_tile_lags()) b.ritems.push_back(make_int4(q, n0, l0, 0));

@@ -260,6 +260,11 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int W = cm.W, R = W + 1, cap = j.cap, K = j.K, M2 = j.M2, M = j.M2 / 2;
+  // This job trains users k0 .. k0 + K - 1 of a detector with Kt users (the
+  // users are independent given the shared kernel values); the group with
+  // k0 = 0 also writes the dictionary and the state words.
+  const int Kt = j.Kt, k0 = j.k0;
+  const bool lead = k0 == 0;
   const int T = 2 * j.P;
   const int EVS = W > 1 ? W - 1 : 1;
   Lds s = carve(lds_raw, W, KP, M2P);
@@ -337,7 +342,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     for (int i = tid; i < cap * KP; i += kThreads) s.alds[i] = 0.0f;
   } else {
     // Dictionary and coefficients in the model buffers; start from an empty one.
-    for (size_t i = tid; i < (size_t)cap * K; i += kThreads) alpha[i] = 0.0f;
+    for (size_t i = tid; i < (size_t)cap * K; i += kThreads) alpha[(i / K) * Kt + k0 + i % K] = 0.0f;
   }
   if (tid == 0) block_flags = 0;
   int flags = 0;
@@ -354,7 +359,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     s.rwin[tid] = c0;
     s.rwin[R * M2P + tid] = c0;
   }
-  bv = sym[(tid < K ? tid : 0) * 2];
+  bv = sym[(k0 + (tid < K ? tid : 0)) * 2];
 
   // Rows training: the kernel values of the even steps are loaded into
   // kr0 / kw0, those of the odd steps into kr1 / kw1, each two steps ahead
@@ -389,7 +394,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       const bool odd = (n1 & 1) != 0;
       comp_nx = rx[(size_t)(n1 >> 1) * M2 + (odd ? (m < M ? m + M : m - M) : m)];
       comp_sg = tid < M2 ? (odd && m >= M ? -1.0f : 1.0f) : 0.0f;
-      bv_nx = sym[((size_t)(n1 >> 1) * K + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
+      bv_nx = sym[((size_t)(n1 >> 1) * Kt + k0 + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
     }
 
     // ------------------------------------------------------------ phase A
@@ -512,7 +517,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
             for (int k = 0; k < KP; ++k) s.aev[k] = s.alds[k * cap + sn];
           for (int k = 0; k < KP; ++k) s.alds[k * cap + sn] = 0.0f;
         } else {
-          auto arow = alpha + (size_t)sn * K;
+          auto arow = alpha + (size_t)sn * Kt + k0;
           if (evicting)
             for (int k = 0; k < K; ++k) s.aev[k] = arow[k];
           for (int k = 0; k < K; ++k) arow[k] = 0.0f;
@@ -531,7 +536,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
             for (int k = 0; k < KP; ++k) av[b][k] = ok ? s.alds[k * cap + slot] : 0.0f;
           } else {
-            const auto arow = alpha + (size_t)(ok ? slot : 0) * K;
+            const auto arow = alpha + (size_t)(ok ? slot : 0) * Kt + k0;
 #pragma unroll
             for (int k = 0; k < KP; ++k) av[b][k] = (ok && k < K) ? arow[k] : 0.0f;
           }
@@ -616,7 +621,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       const float om = s.omega[p];
       float aold = 0.0f;
       if constexpr (SLOTS == 0) aold = s.alds[k * cap + slot];
-      if constexpr (SLOTS < 0) aold = alpha[(size_t)slot * K + (k < K ? k : 0)];
+      if constexpr (SLOTS < 0) aold = alpha[(size_t)slot * Kt + k0 + (k < K ? k : 0)];
 
       // new member: the reduced partial sums; older members: the running
       // value less the evicted entry's Gaussian term (selects, no branch)
@@ -635,7 +640,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         // (member, user) pair per thread; the barrier below orders it
         // before every later read.
         if constexpr (SLOTS == 0) s.alds[k * cap + slot] = fmaf(c, cm.wg, aold);
-        if constexpr (SLOTS < 0) alpha[(size_t)slot * K + k] = fmaf(c, cm.wg, aold);
+        if constexpr (SLOTS < 0) alpha[(size_t)slot * Kt + k0 + k] = fmaf(c, cm.wg, aold);
       }
       s.c[jw * CS + k] = c;
       s.c[(jw + W) * CS + k] = c;
@@ -718,14 +723,15 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
           // the slot holds sample T-1 - lag (lag of the slot after the last step), if written
           const int lag = ring_sub((T - 1) % cap, slot, cap);
           const int i = T - 1 - lag;
-          for (int mm = 0; mm < M2; ++mm)
-            dict[(size_t)mm * cap + slot] = i >= 0 ? sample_comp(rx, M2, M, i, mm) : 0.0f;
+          if (lead)
+            for (int mm = 0; mm < M2; ++mm)
+              dict[(size_t)mm * cap + slot] = i >= 0 ? sample_comp(rx, M2, M, i, mm) : 0.0f;
         } else {
 #pragma unroll
           for (int mm = 0; mm < M2P; ++mm)
             if (mm < M2) dict[(size_t)mm * cap + slot] = dreg[u][mm];
         }
-        auto arow = alpha + (size_t)slot * K;
+        auto arow = alpha + (size_t)slot * Kt + k0;
 #pragma unroll
         for (int k = 0; k < KP; ++k)
           if (k < K) arow[k] = areg[u][k];
@@ -738,23 +744,28 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     if constexpr (SLOTS == 0)
       for (int i = tid; i < cap * K; i += kThreads) {
         const int slot = i / K, k = i - slot * K;
-        alpha[i] = s.alds[k * cap + slot];
+        alpha[(size_t)slot * Kt + k0 + k] = s.alds[k * cap + slot];
       }
   }
   if (wowner) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int k = 4 * grp + v;
-      if (k < K && wm < M2) wout[k * M2 + wm] = cm.wl * wacc[v];
+      if (k < K && wm < M2) wout[(k0 + k) * M2 + wm] = cm.wl * wacc[v];
     }
   }
   if (flags) atomicOr(&block_flags, flags);
   __syncthreads();
   if (tid == 0) {
-    state[0] = T < cap ? T : cap;
-    state[1] = T % cap;
-    state[2] = T;
-    state[3] = block_flags;
+    if (lead) {
+      state[0] = T < cap ? T : cap;
+      state[1] = T % cap;
+      state[2] = T;
+    }
+    // A detector trained as one job overwrites its flags word; the groups of
+    // a split detector OR theirs into it (cleared by the kernel-rows launch).
+    if (K == Kt) state[3] = block_flags;
+    else atomicOr(j.state + 3, block_flags);
   }
 }
 
@@ -774,6 +785,8 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   j.P = a.P;
   j.M2 = a.M2;
   j.K = a.K;
+  j.Kt = a.K;
+  j.k0 = 0;
   j.cap = a.cap;
   j.c2 = a.c2;
   j.variant = 0;
@@ -859,7 +872,8 @@ __global__ __launch_bounds__(kThreads) void train_table_kernel(const TrainJob* j
   APSM_ROWS_VARIANTS_M(X, 16, 32, 8) APSM_ROWS_VARIANTS_M(X, 20, 32, 16)         \
   APSM_ROWS_VARIANTS_M(X, 24, 64, 4) APSM_ROWS_VARIANTS_M(X, 28, 64, 8)          \
   APSM_ROWS_VARIANTS_M(X, 32, 64, 16) APSM_ROWS_VARIANTS_M(X, 36, 128, 4)        \
-  APSM_ROWS_VARIANTS_M(X, 40, 128, 8) APSM_ROWS_VARIANTS_M(X, 44, 128, 16)
+  APSM_ROWS_VARIANTS_M(X, 40, 128, 8) APSM_ROWS_VARIANTS_M(X, 44, 128, 16)       \
+  X(48, 16, 4, 16) X(49, 32, 4, 16) X(50, 64, 4, 16) X(51, 128, 4, 16)
 
 __global__ __launch_bounds__(kThreads) void train_rows_kernel(const TrainJob* jobs, TrainCommon cm) {
   extern __shared__ float lds_raw[];
@@ -929,6 +943,8 @@ __global__ __launch_bounds__(kRowsLags) void kernel_rows_kernel(const TrainJob* 
         if (at[u] >= 0) dst[at[u]] = sg[u] * v[u];
     }
   };
+  // the training groups of a detector OR their flags into a cleared word
+  if (n0 == 0 && l0 == 0 && threadIdx.x == 0) to_global(j.state)[3] = 0;
   stage(kRowsTile * M2, n0, rs, M2);
   stage(kRowsSamples * M2, ilo, xs, S);
   __syncthreads();
@@ -1009,13 +1025,16 @@ bool train_in_table(int M2) { return M2 <= 64; }
 
 int train_rows_variant(int M2, int K, int cap) {
   const int need = (cap + kThreads - 1) / kThreads;
-  if (M2 > 128 || K > 16 || need > 8) return -1;
+  if (M2 > 128 || K > 16 || need > 16 || (need > 8 && K > 4)) return -1;
   const int M2P = m2p_for(M2), KP = kp_for(K);
   const int mi = M2P == 16 ? 0 : M2P == 32 ? 1 : M2P == 64 ? 2 : 3;
+  if (need > 8) return 48 + mi;               // 16 slots per thread, four users
   const int ki = KP == 4 ? 0 : KP == 8 ? 1 : 2;
   const int si = need <= 1 ? 0 : need <= 2 ? 1 : need <= 4 ? 2 : 3;
   return (mi * 3 + ki) * 4 + si;
 }
+
+int train_rows_max_users(int cap) { return (cap + kThreads - 1) / kThreads > 8 ? 4 : 16; }
 
 size_t train_rows_lds_bytes(int W, int M2, int K) { return lds_floats(W, kp_for(K), m2p_for(M2)) * sizeof(float); }
 

@@ -75,7 +75,7 @@ int apsm_train_noalloc(const apsm_params_t* p, int M2, int K, int P, const float
   if (model->M2 != M2 || model->K != K || model->dict_cap != p->dict_cap) return APSM_ERR_SHAPE;
   const int cap = p->dict_cap, W = p->window, T = 2 * P;
   const int variant = train_rows_variant(M2, K, cap);
-  if (variant < 0) return APSM_ERR_UNSUPPORTED;
+  if (variant < 0 || cap > 4096) return APSM_ERR_UNSUPPORTED;
   const int ts = kernel_rows_tile_steps(), tl = kernel_rows_tile_lags();
   const long long lag_tiles = (cap + tl - 1) / tl, step_tiles = (T + ts - 1) / ts;
   const long long n_items = lag_tiles * step_tiles;
@@ -100,6 +100,8 @@ int apsm_train_noalloc(const apsm_params_t* p, int M2, int K, int P, const float
   j.P = P;
   j.M2 = M2;
   j.K = K;
+  j.Kt = K;
+  j.k0 = 0;
   j.cap = cap;
   j.c2 = kLog2e / (2.0f * p->sigma2);
   j.variant = variant;
