@@ -889,85 +889,129 @@ __global__ __launch_bounds__(kThreads) void train_rows_kernel(const TrainJob* jo
   }
 }
 
-// Kernel rows of kRowsTile training steps and kRowsLags lags per
-// workgroup: item (job, n0, l0) writes, for n0 <= n < n0 + kRowsTile and
-// l0 <= l < l0 + kRowsLags (thread l - l0), glag[n][l] = kappa_G(r_n, r_{n-l})
-// (0 for l > n), from the squared distance accumulated component by
-// component, and for l < W the window Gram entry
-// kw[n][l] = wL r_n.r_{n-l} + wG kappa_G(r_n, r_{n-l}).  The tile's steps
-// and the samples r_{n-l} it needs are staged in LDS first (sample rows at
-// an odd stride, so that the lanes' strided reads hit distinct banks).
-constexpr int kRowsTile = 16;
-constexpr int kRowsLags = 256;
-constexpr int kRowsSamples = kRowsTile + kRowsLags - 1;
+// Kernel rows: item (job, n0, l0) writes, for the steps n0 <= n < n0 + 128
+// and the lags l0 <= l < l0 + 128,
+//   glag[n][l] = kappa_G(r_n, r_{n-l})   (0 for l > n)
+// and for l < W the window Gram entry kw[n][l] = wL r_n.r_{n-l} + wG kappa_G(r_n, r_{n-l}).
+// The products r_n.r_i of the tile form a 128 x 255 band of a Gram matrix:
+// wave w computes the 16 steps n0 + 16 w .. n0 + 16 w + 15 against the nine
+// 16-sample column tiles that its lags reach, on v_mfma_f32_16x16x4_f32
+// (steps as rows, samples as columns).  Lane (c, g) of a column tile holds
+// components g Q .. g Q + Q - 1 (Q = M2R / 4) of its step (A operand, in
+// registers) and of its sample (B operand, read from LDS four at a time), so
+// MFMA s contracts component g Q + s over the four lane groups.  The 256
+// samples the workgroup needs are staged in LDS with their squared norms;
+// kappa_G = exp2(-c2 max(0, ||r_n||^2 + ||r_i||^2 - 2 r_n.r_i)), and exactly 1
+// at lag 0 (with r_n.r_n taken as ||r_n||^2).
+constexpr int kRowsTile = 128;              // steps per workgroup
+constexpr int kRowsLags = 128;              // lags per workgroup
+constexpr int kRowsThreads = 512;           // eight waves, 16 steps each
+constexpr int kRowsSamples = 256;           // kRowsTile + kRowsLags - 1, padded to 16 column tiles
 
-size_t kernel_rows_lds_floats(int M2) { return (size_t)kRowsTile * M2 + (size_t)kRowsSamples * (M2 + 1); }
+__host__ __device__ constexpr int rows_m2r(int M2) { return M2 <= 16 ? 16 : M2 <= 32 ? 32 : M2 <= 64 ? 64 : 128; }
+size_t kernel_rows_lds_floats(int M2) { return (size_t)kRowsSamples * (rows_m2r(M2) + 4) + kRowsSamples; }
 
-__global__ __launch_bounds__(kRowsLags) void kernel_rows_kernel(const TrainJob* jobs, const int4* items,
-                                                                TrainCommon cm) {
+template <int M2R>
+__global__ __launch_bounds__(kRowsThreads) void kernel_rows_kernel(const TrainJob* jobs, const int4* items,
+                                                                   TrainCommon cm) {
+  constexpr int Q = M2R / 4, STR = M2R + 4;  // STR = 4 (mod 64): conflict-free column-tile reads
   extern __shared__ float rows_lds[];
+  float* xs = rows_lds;                      // [kRowsSamples][STR] samples ilo ..
+  float* xn = rows_lds + kRowsSamples * STR; // their squared norms
   const int4 it = items[blockIdx.x];
   const TrainJob& j = jobs[it.x];
   const int n0 = it.y, l0 = it.z;
-  const int M2 = j.M2, M = M2 / 2, cap = j.cap, W = cm.W, T = 2 * j.P, S = M2 + 1;
-  float* rs = rows_lds;                                  // [kRowsTile][M2] steps n0..
-  float* xs = rows_lds + kRowsTile * M2;                 // [kRowsSamples][S] samples ilo..
+  const int M2 = j.M2, M = M2 / 2, cap = j.cap, W = cm.W, T = 2 * j.P;
   const int ilo = n0 - l0 - (kRowsLags - 1);
-  // Staging: branch-free loads (clamped sample index; the sign of an r2
-  // component and the validity mask applied at the store) in unrolled
-  // loops, so that several loads are in flight before the first store
-  // waits for its data.
-  const auto rx = to_global(j.rx);
-  auto comp = [&](int i, int m, float& sg) {
-    const bool ok = i >= 0 && i < T, odd = (i & 1) != 0;
-    const int ic = ok ? i : 0;
-    sg = ok ? (odd && m >= M ? -1.0f : 1.0f) : 0.0f;
-    return rx[(size_t)(ic >> 1) * M2 + (odd ? (m < M ? m + M : m - M) : m)];
-  };
-  // element e of a staging region: vector e / M2 (first index i0), component e % M2
-  auto stage = [&](int count, int i0, float* dst, int stride) {
-    constexpr int B = 8;
-    for (int e0 = threadIdx.x; e0 < count; e0 += B * kRowsLags) {
-      float v[B], sg[B];
-      int at[B];
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const int e = e0 + u * kRowsLags;
-        const int ec = e < count ? e : e0;
-        const int q = ec / M2, m = ec - q * M2;
-        v[u] = comp(i0 + q, m, sg[u]);
-        at[u] = e < count ? q * stride + m : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < B; ++u)
-        if (at[u] >= 0) dst[at[u]] = sg[u] * v[u];
-    }
-  };
   // the training groups of a detector OR their flags into a cleared word
   if (n0 == 0 && l0 == 0 && threadIdx.x == 0) to_global(j.state)[3] = 0;
-  stage(kRowsTile * M2, n0, rs, M2);
-  stage(kRowsSamples * M2, ilo, xs, S);
-  __syncthreads();
-  const int l = l0 + threadIdx.x;
-  if (l >= cap) return;
-  for (int r = 0; r < kRowsTile; ++r) {
-    const int n = n0 + r;
-    if (n >= T) break;
-    const int i = n - l;
-    float kg = 0.0f, dot = 0.0f;
-    if (i >= 0) {
-      const float* a = rs + r * M2;
-      const float* x = xs + (i - ilo) * S;
-      float d2 = 0.0f;
-      for (int m = 0; m < M2; ++m) {
-        const float d = a[m] - x[m];
-        d2 = fmaf(d, d, d2);
-        dot = fmaf(a[m], x[m], dot);
+  const auto rx = to_global(j.rx);
+  // component m of training vector i (0 outside the sequence or the width):
+  // a clamped, unconditional load and a sign/mask applied afterwards
+  auto comp = [&](int i, int m) {
+    const bool ok = i >= 0 && i < T && m < M2, odd = (i & 1) != 0;
+    const int ic = ok ? i : 0, mc = m < M2 ? m : 0;
+    const float sg = ok ? (odd && mc >= M ? -1.0f : 1.0f) : 0.0f;
+    return sg * rx[(size_t)(ic >> 1) * M2 + (odd ? (mc < M ? mc + M : mc - M) : mc)];
+  };
+  {
+    constexpr int B = 8;                     // loads in flight per thread
+    constexpr int N = kRowsSamples * M2R;
+    for (int e0 = threadIdx.x; e0 < N; e0 += B * kRowsThreads) {
+      float v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = e0 + u * kRowsThreads;
+        const int ec = e < N ? e : e0;
+        v[u] = comp(ilo + ec / M2R, ec % M2R);
       }
-      kg = __builtin_amdgcn_exp2f(-j.c2 * d2);
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = e0 + u * kRowsThreads;
+        if (e < N) xs[(e / M2R) * STR + e % M2R] = v[u];
+      }
     }
-    to_global(j.glag)[(size_t)n * cap + l] = kg;
-    if (l < W) to_global(j.kw)[(size_t)n * W + l] = i >= 0 ? fmaf(cm.wl, dot, cm.wg * kg) : 0.0f;
+  }
+  __syncthreads();
+  if (threadIdx.x < kRowsSamples) {
+    const float* x = xs + threadIdx.x * STR;
+    float n4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int m = 0; m < M2R; ++m) n4[m & 3] = fmaf(x[m], x[m], n4[m & 3]);
+    xn[threadIdx.x] = (n4[0] + n4[1]) + (n4[2] + n4[3]);
+  }
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  // A operand: step n0 + 16 w + c, components g Q .. g Q + Q - 1
+  float a[Q];
+  float an = 0.0f;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    a[s] = comp(n0 + 16 * w + c, g * Q + s);
+    an = fmaf(a[s], a[s], an);
+  }
+  an += __shfl_xor(an, 16);
+  an += __shfl_xor(an, 32);                  // ||r_{n0+16w+c}||^2 in every lane of column c
+  float nn[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) nn[i] = __shfl(an, 4 * g + i);   // steps 16 w + 4 g + i
+  __syncthreads();
+
+  floatx4 acc[9];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) acc[u] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int s0 = 0; s0 < Q; s0 += 4) {
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+      const floatx4 b4 = *reinterpret_cast<const floatx4*>(xs + (16 * (w + u) + c) * STR + g * Q + s0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s0 + t], b4[t], acc[u], 0, 0, 0);
+    }
+  }
+
+  // outputs: acc[u] lane (c, g) row i = step n0 + 16 w + 4 g + i against sample
+  // ilo + 16 (w + u) + c, i.e. lag l0 + 127 + 4 g + i - 16 u - c
+  auto glag = to_global(j.glag);
+  auto kwg = to_global(j.kw);
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    const int q = 16 * (w + u) + c;          // staged sample
+    const float xq = xn[q];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * w + 4 * g + i, n = n0 + r;
+      const int lr = kRowsLags - 1 + 4 * g + i - 16 * u - c;   // lag - l0
+      const int lag = l0 + lr;
+      if (lr < 0 || lr >= kRowsLags || lag >= cap || n >= T) continue;
+      const bool inseq = n - lag >= 0;
+      const float dot = lag == 0 ? nn[i] : acc[u][i];
+      const float d2 = fmaxf(nn[i] + xq - 2.0f * dot, 0.0f);
+      const float kg = !inseq ? 0.0f : lag == 0 ? 1.0f : __builtin_amdgcn_exp2f(-j.c2 * d2);
+      glag[(size_t)n * cap + lag] = kg;
+      if (lag < W) kwg[(size_t)n * W + lag] = inseq ? fmaf(cm.wl, dot, cm.wg * kg) : 0.0f;
+    }
   }
 }
 
@@ -1041,15 +1085,29 @@ size_t train_rows_lds_bytes(int W, int M2, int K) { return lds_floats(W, kp_for(
 int kernel_rows_tile_steps() { return kRowsTile; }
 int kernel_rows_tile_lags() { return kRowsLags; }
 
+template <int M2R>
+static hipError_t launch_rows_m(const TrainJob* jobs, const int4* items, int n_items, const TrainCommon& cm,
+                                hipStream_t stream) {
+  const size_t bytes = kernel_rows_lds_floats(M2R) * sizeof(float);
+  auto kern = kernel_rows_kernel<M2R>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n_items), dim3(kRowsThreads), bytes, stream, jobs, items, cm);
+  return hipGetLastError();
+}
+
+// Every job of one launch runs with the width of the widest (max_M2): the
+// components past a job's 2M are zeros.
 hipError_t launch_kernel_rows(const TrainJob* jobs, const int4* items, int n_items, int max_M2,
                               const TrainCommon& cm, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  const size_t bytes = kernel_rows_lds_floats(max_M2) * sizeof(float);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel_rows_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kernel_rows_kernel, dim3(n_items), dim3(kRowsLags), bytes, stream, jobs, items, cm);
-  return hipGetLastError();
+  switch (rows_m2r(max_M2)) {
+    case 16: return launch_rows_m<16>(jobs, items, n_items, cm, stream);
+    case 32: return launch_rows_m<32>(jobs, items, n_items, cm, stream);
+    case 64: return launch_rows_m<64>(jobs, items, n_items, cm, stream);
+    default: return launch_rows_m<128>(jobs, items, n_items, cm, stream);
+  }
 }
 
 hipError_t launch_train_rows(const TrainJob* jobs, int n, const TrainCommon& cm, size_t lds_bytes,
