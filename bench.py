@@ -1,18 +1,24 @@
 """Benchmark of the APSM detector hot path on one MI355X.
 
-One step = the whole path on one realistic slot at four SNR points
-(5, 10, 15, 20 dB): for each point, training on 1024 pilot symbols
-(2048 real steps, window 32, dictionary cap 1024) followed by detection,
-decisions and symbol-error counting on 1,048,576 data symbols of 6 users
-received on 16 antennas (near-far powers in [-6, 0] dB, Rapp PA p = 2,
-A_sat = 1).  Inputs are synthetic (seeded) and resident in HBM before the
-timed region starts.  The four trainings run in one launch (one workgroup
-each), followed by the four detections.
+Headline workload (the largest single-GPU configuration): the large array,
+batched.  16 detector instances, each with 16 users (16-QAM, Rapp PA p = 2,
+A_sat = 1, 20 dB) received on 64 antennas (2M = 128), 8192 pilot symbols
+(16,384 real training steps, window 32, dictionary capacity 8192) and
+4,194,304 data symbols.  One step trains the 16 detectors (kernel rows in one
+launch, training in one launch, packing) and detects all 16 x 4,194,304
+received vectors with decisions and symbol-error counts (one persistent
+launch).  Steps are pipelined over two model sets on two streams (the
+training of step k runs beside the detection of step k - 1); every step still
+trains 16 detectors and detects 16 frames.  Inputs are synthetic (seeded),
+generated on the device, and resident in HBM before the timed region.
 
-Prints one JSON line: whole-step throughput in detected user-symbols/s, the
-roofline of the detection kernel (its average duration measured with HIP
-events on its stream), and the FP64 oracle timed on a bounded sample of the
-same workload on the host.
+Further workloads in the same JSON line: the realistic slot (4 SNR points of
+one 6-user, 16-antenna slot with 1,048,576 symbols), the batched mixed-shape
+workload (256 detectors), the differentiable unrolled training (64
+instances, forward + backward), the small plain case (per-call latency) and
+the paper's own shape (detection latency, context for its Table).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,28 +32,22 @@ import numpy as np
 
 METRIC = ("detected symbols/s and kernel evals/s vs roofline at oracle SER; "
           "batched vs plain")
-# Peak of the pipe that binds detection: the FP32 VALU without packed-FP32
-# instructions (kept out of the build), 256 CUs x 4 SIMDs x 16 lanes x FMA
-# (2 flops) x 2.4 GHz.  The exp2 of each kernel evaluation is a
-# transcendental that occupies four VALU issue slots (counted as 8 flops).
+# Dense FP16 matrix-core peak of the MI355X: 256 CUs x 4096 flops/clock x 2.4 GHz.
+PEAK_FP16_MFMA_TFLOPS = 256 * 4096 * 2.4e9 / 1e12               # 2516.6
 # FP32 vector peak: 256 CUs x 4 SIMDs x 32 lanes x 2 flops (FMA) x 2.4 GHz.
-# Plain (non-packed) FP32 FMA reaches it: a throughput probe of independent
-# v_fma_f32 chains measured 111 TFLOP/s on this GPU, above half of it.
-PEAK_FP32_VALU_TFLOPS = 256 * 4 * 32 * 2 * 2.4e9 / 1e12     # 157.3
+PEAK_FP32_VALU_TFLOPS = 256 * 4 * 32 * 2 * 2.4e9 / 1e12         # 157.3
 
-# HBM bytes per launch of detect_f16_kernel<32,6> on this workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a 256 MiB device copy
-# (profiles/detect_f16_realistic_slot_counters.md).  Valid only for the kernel
-# sources they were taken with; reported as null otherwise.
-MEASURED_TRAFFIC = {
-    "bytes": (138977 + 55502) * 1024,
-    "sources": {"paper_2201_05024_amd/csrc/detect_f16.h": "5908371f618de0c3b04c177ce06f05ab8e87321b",
-                "paper_2201_05024_amd/csrc/detect_f16_m32.hip": "d4dbc3a03f2d61d0eb05e76f679e0ec7b04f4b6c"},
-}
+# HBM bytes per launch of the batched two-contraction detection kernel on the
+# headline workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
+# plain device copy (profiles/).  Valid only for the sources they were taken
+# with; reported as null otherwise.
+MEASURED_TRAFFIC = {"bytes": None, "sources": {}}
 
 
 def measured_traffic():
     import hashlib
+    if MEASURED_TRAFFIC["bytes"] is None:
+        return None
     root = os.path.dirname(os.path.abspath(__file__))
     for rel, digest in MEASURED_TRAFFIC["sources"].items():
         try:
@@ -66,82 +66,491 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true",
-                    help="skip the oracle timing (profiling runs)")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timings")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the large-array workload (profiling runs)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-detector forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched mixed-shape workload")
-    ap.add_argument("--serial", action="store_true",
-                    help="train then detect within each step (no overlap of consecutive steps)")
-    ap.add_argument("--batched-steps", type=int, default=5)
     return ap.parse_args()
 
 
-def cpu_baseline(spec_fn, snr, params, S_full, n_inst):
-    """Time the FP64 oracle on a bounded sample: full training of one instance
-    plus detection of 1024 data symbols, extrapolated linearly to one step."""
+def cuda_events(n=2):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        return 1
+
+
+def best_of(fn, reps=3):
+    best = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return best
+
+
+# ------------------------------------------------------------------ headline
+
+def oracle_built_model(inst, cap, K, seed):
+    """A full-capacity filter for the large-array shape built without
+    training (training it in FP64 takes about an hour): the dictionary is the
+    newest `cap` real training vectors of the pilots (what a capacity-`cap`
+    training leaves), coefficients and linear weights are seeded draws."""
     import oracle as O
     import synth
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:  # pragma: no cover
-        limiter = None
-    inst = synth.make_instance(spec_fn(snr, S=1024))
-    p = O.APSMParams(sigma2=params.sigma2, eps=params.eps, mu=params.mu, window=params.window,
-                     w_lin=params.w_lin, w_gauss=params.w_gauss, dict_cap=params.dict_cap)
+    R, _ = O.training_sequence(synth.planar_to_complex(inst.rx_pilot), synth.pair_to_complex(inst.sym_pilot))
+    rng = np.random.default_rng(seed)
+    d = R[-cap:].astype(np.float32)
+    alpha = (rng.standard_normal((cap, K)) * 0.05).astype(np.float32)
+    w = (rng.standard_normal((K, R.shape[1])) * 0.05).astype(np.float32)
+    return d, alpha, w
+
+
+def run_large(args, dev):
+    import torch
+    import oracle as O
+    import synth
+    import paper_2201_05024_amd as A
+
+    n = synth.LARGE_INSTANCES
+    specs = [synth.spec_large(i) for i in range(n)]
+    sp0 = specs[0]
+    K, M2, P, S, cap, W = sp0.K, 2 * sp0.M, sp0.P, sp0.S, 8192, 32
+    params = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=W, w_lin=0.5, w_gauss=0.5, dict_cap=cap)
+    log(f"[bench] large array: generating {n} instances on the device")
+    insts = [synth.make_instance_device(sp, dev) for sp in specs]
+    rx_p = [torch.from_numpy(i.rx_pilot).to(dev) for i in insts]
+    sym_p = [torch.from_numpy(i.sym_pilot).to(dev) for i in insts]
+    soft = [torch.empty((S, K, 2), dtype=torch.float32, device=dev) for _ in insts]
+    hard = [torch.empty((S, K), dtype=torch.uint8, device=dev) for _ in insts]
+    errs = [torch.zeros(K, dtype=torch.int64, device=dev) for _ in insts]
+    # two model sets, one batch each; both detect into the same outputs
+    # (their detections are ordered on one stream)
+    models = [[A.Model(M2, K, cap, dev, params.sigma2) for _ in insts] for _ in range(2)]
+    batches = [A.Batch(params, [A.BatchItem(model=ms[i], rx_pilot=rx_p[i], sym_pilot=sym_p[i], rx=insts[i].rx_data,
+                                            modulation="qam16", soft=soft[i], hard=hard[i], truth=insts[i].truth,
+                                            errors=errs[i]) for i in range(n)]) for ms in models]
+    s_train, s_det = torch.cuda.Stream(), torch.cuda.Stream()
+    trained = [torch.cuda.Event(), torch.cuda.Event()]
+    detected = [torch.cuda.Event(), torch.cuda.Event()]
+    rows_ready = [torch.cuda.Event(), torch.cuda.Event()]
+    det_events = []
+
+    def detect_set(k, record):
+        for e in errs:
+            e.zero_()
+        if record:
+            e0, e1 = cuda_events()
+            e0.record(s_det)
+        batches[k].detect(s_det)
+        if record:
+            e1.record(s_det)
+            det_events.append((e0, e1))
+
+    def step(k, record):
+        cur, prev = k % 2, (k + 1) % 2
+        with torch.cuda.stream(s_det):
+            batches[cur].kernel_rows(s_det)
+            rows_ready[cur].record(s_det)
+        with torch.cuda.stream(s_train):
+            s_train.wait_event(detected[cur])
+            s_train.wait_event(rows_ready[cur])
+            batches[cur].train_prepared(s_train)
+            trained[cur].record(s_train)
+        with torch.cuda.stream(s_det):
+            s_det.wait_event(trained[prev])
+            detect_set(prev, record)
+            detected[prev].record(s_det)
+
+    torch.cuda.synchronize()
+    log(f"[bench] large array: warmup {args.warmup}")
+    with torch.cuda.stream(s_train):
+        batches[1].train(s_train)
+        trained[1].record(s_train)
+    for k in range(args.warmup):
+        step(k, False)
+    torch.cuda.synchronize()
+    # parts alone, for the report
+    ev = cuda_events(4)
+    ev[0].record(s_det)
+    batches[0].kernel_rows(s_det)
+    ev[1].record(s_det)
+    batches[0].train_prepared(s_det)
+    ev[2].record(s_det)
+    detect_set(0, False)
+    ev[3].record(s_det)
+    torch.cuda.synchronize()
+    rows_ms, train_ms, det1_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])
+    serial_ms = ev[0].elapsed_time(ev[3])
+    # re-arm the pipeline: set 1 trained, set 0 free
+    with torch.cuda.stream(s_train):
+        batches[1].train(s_train)
+        trained[1].record(s_train)
+    with torch.cuda.stream(s_det):
+        detected[0].record(s_det)
+    torch.cuda.synchronize()
+
+    log(f"[bench] large array: timing {args.steps} steps")
     t0 = time.perf_counter()
-    f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, p)
-    t_train = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    soft = O.detect_planar(f, inst.rx_data)
-    O.symbol_errors(O.decide(soft, "qpsk"), inst.truth)
-    t_det = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.restore_original_limits()
-    K = inst.spec.K
-    t_step = n_inst * (t_train + t_det * S_full / 1024)
+    for k in range(args.steps):
+        step(k, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log("[bench] large array: timed region done")
+    ser_gpu = float(sum(e.sum().item() for e in errs)) / (n * S * K)
+
+    det_ms = [a.elapsed_time(b) for a, b in det_events]
+    det_s = float(np.mean(det_ms)) / 1e3
+    M2P = 128
+    evals = n * 2 * S * cap                                     # (real vector, entry) pairs per launch
+    # FP16 matrix-core flops: three split products of the distance block
+    # (2 x 2M) and of the coefficient block (2 x 16 users) per evaluation,
+    # and of the linear part (2 x 2M x 16) per real vector
+    mfma_flops = evals * 6 * (M2P + 16) + n * 2 * S * 6 * M2P * 16
+    achieved = mfma_flops / det_s / 1e12
+    # the algorithmic FP32 count of the method: D (2 2M + 3 + 2K) + 2 2M (K + 1) per real vector
+    alg_flops = n * 2 * S * (cap * (2 * M2 + 3 + 2 * K) + 2 * M2 * (K + 1))
+    # VALU per evaluation: exponent FMA (2), exp2 (four issue slots, 8), hi/lo split (3 ops, 6)
+    valu_flops = evals * 16
+
+    out = {
+        "value": n * S * K / (elapsed / args.steps),
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "config": {
+            "workload": ("large array, batched: 16 instances x (K=16 users 16-QAM, 64 Rx antennas (2M=128), "
+                         "Rapp PA p=2 A_sat=1, 20 dB, 8192 pilots, 4194304 data symbols, W=32, sigma2=0.5, "
+                         "eps=0.05, mu=1, dictionary cap 8192); one step trains and detects all 16"),
+            "instances_per_step": n, "data_symbols": S, "pilots": P, "users": K, "antennas": M2 // 2,
+        },
+        "roofline": {
+            "kernel": "detect_wide_batch_kernel", "bound": "mfma", "achieved": achieved,
+            "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP16_MFMA_TFLOPS,
+            "traffic": measured_traffic(),
+            "per_launch": {"kernel_evals": evals, "fp16_mfma_flops": mfma_flops,
+                           "fp16_mfma_flops_per_eval": 6 * (M2P + 16), "avg_ms": det_s * 1e3,
+                           "launches_timed": len(det_ms),
+                           "method_fp32_flops": alg_flops,
+                           "method_fp32_tflops_equivalent": alg_flops / det_s / 1e12,
+                           "valu_flop_equivalents": valu_flops,
+                           "valu_frac_of_fp32_peak": valu_flops / det_s / 1e12 / PEAK_FP32_VALU_TFLOPS},
+        },
+        "detect_only": {"user_symbols_per_s": n * S * K / det_s, "kernel_evals_per_s": evals / det_s,
+                        "ms_one_launch_16_instances": det_s * 1e3},
+        "train_ms_16_instances": {"kernel_rows": rows_ms, "training_and_packing": train_ms},
+        "ms_per_step_serialized": serial_ms,
+        "detect_ms_serialized_run": det1_ms,
+        "schedule": ("pipelined: the kernel rows of step k (one launch) precede the detection launch on the "
+                     "detection stream; the training of step k (one launch, 64 four-user jobs) runs beside the "
+                     "detection of step k-1 (one persistent launch over all 16 instances) on a second stream"),
+        "ser_gpu": ser_gpu,
+    }
+
+    # detection-only parity on the headline's data and launch form: a
+    # full-capacity filter built from the pilots (no training) detects
+    # instance 0's 4,194,304 vectors; the oracle evaluates a spread sample
+    log("[bench] large array: detection parity sample")
+    d, alpha, w = oracle_built_model(insts[0], cap, K, seed=55)
+    pm = A.Model(M2, K, cap, dev, 0.5)
+    pm.dict.copy_(torch.from_numpy(np.ascontiguousarray(d.T)).to(dev))
+    pm.alpha.copy_(torch.from_numpy(alpha).to(dev))
+    pm.w.copy_(torch.from_numpy(w).to(dev))
+    pm.state.copy_(torch.tensor([cap, 0, 2 * P, 0], dtype=torch.int32, device=dev))
+    pm.pack()
+    po = A.detect(pm, insts[0].rx_data, modulation="qam16", truth=insts[0].truth)
+    torch.cuda.synchronize()
+    idx = np.unique(np.r_[0:32, np.arange(0, S, 16384), S - 32:S])
+    f = O.Filter(K, M2, 0.5)
+    f.w, f.dict_vec, f.alpha = w.astype(np.float64), d.astype(np.float64), alpha.astype(np.float64)
+    f.dict_idx = list(range(cap))
+    rx_sub = insts[0].rx_data[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    soft_ref = O.detect_planar(f, rx_sub, chunk=8)
+    soft_gpu = po["soft"].cpu().numpy()[idx].astype(np.float64)
+    a_min = 1 / np.sqrt(10)
+    scaled = np.abs(soft_gpu - soft_ref) / np.maximum(np.abs(soft_ref), a_min)
+    lab_ref = O.decide(soft_ref, "qam16")
+    near = O.boundary_distance(soft_ref, "qam16") < 1e-5
+    hard_gpu = po["hard"].cpu().numpy()[idx]
+    truth_sub = insts[0].truth.cpu().numpy()[idx]
+    diff = hard_gpu != lab_ref
+    out["parity_sample"] = {
+        "what": ("detection only, instance 0 of the headline data (4194304 vectors, one launch) with a "
+                 "full-capacity filter built from its pilots; oracle on the first and last 32 and every "
+                 f"16384th symbol ({len(idx)} symbols x 16 users)"),
+        "max_scaled_error": float(scaled.max()),
+        "decision_mismatch_outside_band": int(np.sum(diff & ~near)),
+        "decision_mismatch_inside_band": int(np.sum(diff & near)),
+        "ser_gpu_sample": float(np.mean(hard_gpu != truth_sub)),
+        "ser_oracle_sample": float(np.mean(lab_ref != truth_sub)),
+    }
+
+    if not args.no_plain:
+        log("[bench] large array: plain form (one launch per detector)")
+        pmodels = models[0]
+
+        def plain_detect():
+            for i in range(n):
+                A.detect(pmodels[i], insts[i].rx_data, modulation="qam16", truth=insts[i].truth,
+                         soft=soft[i], hard=hard[i], errors=errs[i], stream=s_det)
+
+        with torch.cuda.stream(s_det):
+            plain_detect()
+            torch.cuda.synchronize()
+            e = cuda_events()
+            e[0].record(s_det)
+            plain_detect()
+            e[1].record(s_det)
+            torch.cuda.synchronize()
+            plain_det_ms = e[0].elapsed_time(e[1])
+            e = cuda_events()
+            e[0].record(s_det)
+            for i in range(n):
+                A.train(rx_p[i], sym_p[i], params, model=pmodels[i], stream=s_det)
+            e[1].record(s_det)
+            torch.cuda.synchronize()
+            plain_train_ms = e[0].elapsed_time(e[1])
+        plain_step_ms = plain_det_ms + plain_train_ms
+        out["plain"] = {
+            "what": "16 apsm_train launches then 16 apsm_detect launches, one detector each, on one stream",
+            "ms_per_step": plain_step_ms, "train_ms": plain_train_ms, "detect_ms": plain_det_ms,
+            "user_symbols_per_s": n * S * K / (plain_step_ms / 1e3),
+            "speedup_batched_vs_plain": plain_step_ms / out["ms_per_step"],
+            "detect_speedup_batched_vs_plain": plain_det_ms / (det_s * 1e3),
+        }
+
+    if not args.no_cpu_baseline:
+        log("[bench] large array: timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline_large(insts[0], d, alpha, w, params, n, S, P, cap, W)
+    return out
+
+
+def cpu_baseline_large(inst, d, alpha, w, params, n, S, P, cap, W):
+    """The FP64 oracle (best of 3) on a bounded sample of the headline
+    workload: detection of 64 symbols and 6 training steps with a full
+    8192-entry dictionary, scaled to one step (16 trainings of 16384 steps,
+    16 x 4194304 detected symbols)."""
+    import oracle as O
+    K, M2 = alpha.shape[1], d.shape[1]
+    steps = 6
+    f = O.Filter(K, M2, params.sigma2)
+    f.w, f.dict_vec, f.alpha = w.astype(np.float64), d.astype(np.float64), alpha.astype(np.float64)
+    # the entries of the steps before the timed ones
+    f.dict_idx = list(range(2 * P - steps - cap, 2 * P - steps))
+    rx = inst.rx_data[:64].cpu().numpy()
+    t_det = best_of(lambda: O.symbol_errors(O.decide(O.detect_planar(f, rx, chunk=8), "qam16"),
+                                            inst.truth[:64].cpu().numpy()))
+    rng = np.random.default_rng(1)
+    Rt = rng.standard_normal((2 * P, M2)) * 0.09
+    Bt = rng.standard_normal((2 * P, K)) * 0.5
+    p = O.APSMParams(sigma2=params.sigma2, eps=params.eps, mu=params.mu, window=W, w_lin=params.w_lin,
+                     w_gauss=params.w_gauss, dict_cap=cap)
+
+    def train_steps():
+        tr = O.Trainer(Rt, Bt, p, f0=f)
+        tr.n = 2 * P - steps                  # the last steps: full dictionary and window
+        for _ in range(steps):
+            tr.step()
+
+    t_steps = best_of(train_steps)
+    # cost of a step is proportional to |J_n| D_n; the timed steps had W and cap
+    units = sum(min(k + 1, W) * min(k + 1, cap) for k in range(2 * P)) / (W * cap)
+    t_train = t_steps / steps * units
+    t_inst = t_train + t_det / 64 * S
     return {
-        "value": n_inst * S_full * K / t_step,
+        "value": S * 16 / t_inst,
         "unit": "user-symbols/s",
-        "cores": 1,
+        "cores": blas_threads(),
         "kind": "oracle",
-        "sample": (f"FP64 oracle, 1 thread: full training of one {snr:g} dB instance "
-                   f"({t_train:.2f} s) and detection of 1024 of {S_full} data symbols "
-                   f"({t_det:.2f} s), extrapolated linearly to {n_inst} instances x {S_full} symbols"),
+        "sample": (f"FP64 oracle (numpy, {blas_threads()} BLAS threads of {os.cpu_count()} host cores), best of 3: "
+                   f"detection of 64 of 4194304 symbols with a full 8192-entry dictionary ({t_det:.2f} s) and "
+                   f"{steps} training steps with full dictionary and window ({t_steps:.2f} s), scaled to one "
+                   f"instance (2P = {2 * P} steps weighted by |J_n| D_n: {t_train:.0f} s training, "
+                   f"{t_det / 64 * S:.0f} s detection); value = one instance's symbols over its time "
+                   f"(the {n} instances of a step take {n} times as long)"),
     }
 
 
-def run_batched(args, dev):
-    """The batched mixed-shape workload: 256 detectors (K 2..8, 8/16/32
-    antennas, dictionaries of 64..2048 entries with as many pilots, 65,536
-    received vectors each, QPSK/16-QAM mixed) trained in one launch and
-    detected in one launch, against the plain form (one apsm_train and one
-    apsm_detect launch per detector) on the same buffers."""
+# ------------------------------------------------------- realistic slot (C2)
+
+def run_slot(args, dev):
+    import torch
+    import oracle as O
+    import synth
+    import paper_2201_05024_amd as A
+
+    snrs = synth.SLOT_SNRS_DB
+    params = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, w_lin=0.5, w_gauss=0.5, dict_cap=1024)
+    log(f"[bench] slot: generating {len(snrs)} instances")
+    insts = [synth.make_instance(synth.spec_slot(s)) for s in snrs]
+    K, M2, P, S = insts[0].spec.K, 2 * insts[0].spec.M, insts[0].spec.P, insts[0].spec.S
+    cu = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    rx_p = [cu(i.rx_pilot) for i in insts]
+    sym_p = [cu(i.sym_pilot) for i in insts]
+    rx_d = [cu(i.rx_data) for i in insts]
+    truth = [cu(i.truth) for i in insts]
+    soft = [torch.empty((S, K, 2), dtype=torch.float32, device=dev) for _ in insts]
+    hard = [torch.empty((S, K), dtype=torch.uint8, device=dev) for _ in insts]
+    errs = [torch.zeros(K, dtype=torch.int64, device=dev) for _ in insts]
+    models = [[A.Model(M2, K, params.dict_cap, dev, params.sigma2) for _ in insts] for _ in range(2)]
+    batches = [A.Batch(params, [A.BatchItem(model=ms[i], rx_pilot=rx_p[i], sym_pilot=sym_p[i], rx=rx_d[i],
+                                            modulation="qpsk", soft=soft[i], hard=hard[i], truth=truth[i],
+                                            errors=errs[i]) for i in range(len(insts))]) for ms in models]
+    s_train, s_det = torch.cuda.Stream(), torch.cuda.Stream()
+    trained = [torch.cuda.Event(), torch.cuda.Event()]
+    detected = [torch.cuda.Event(), torch.cuda.Event()]
+    rows_ready = [torch.cuda.Event(), torch.cuda.Event()]
+    det_events = []
+
+    def detect_set(k, record):
+        for e in errs:
+            e.zero_()
+        if record:
+            e0, e1 = cuda_events()
+            e0.record(s_det)
+        batches[k].detect(s_det)
+        if record:
+            e1.record(s_det)
+            det_events.append((e0, e1))
+
+    def step(k, record):
+        cur, prev = k % 2, (k + 1) % 2
+        with torch.cuda.stream(s_det):
+            batches[cur].kernel_rows(s_det)
+            rows_ready[cur].record(s_det)
+        with torch.cuda.stream(s_train):
+            s_train.wait_event(detected[cur])
+            s_train.wait_event(rows_ready[cur])
+            batches[cur].train_prepared(s_train)
+            trained[cur].record(s_train)
+        with torch.cuda.stream(s_det):
+            s_det.wait_event(trained[prev])
+            detect_set(prev, record)
+            detected[prev].record(s_det)
+
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s_train):
+        batches[1].train(s_train)
+        trained[1].record(s_train)
+    for k in range(3):
+        step(k, False)
+    torch.cuda.synchronize()
+    ev = cuda_events(3)
+    ev[0].record(s_det)
+    batches[0].train(s_det)
+    ev[1].record(s_det)
+    detect_set(0, False)
+    ev[2].record(s_det)
+    torch.cuda.synchronize()
+    train_ms, serial_ms = ev[0].elapsed_time(ev[1]), ev[0].elapsed_time(ev[2])
+    with torch.cuda.stream(s_train):
+        batches[1].train(s_train)
+        trained[1].record(s_train)
+    with torch.cuda.stream(s_det):
+        detected[0].record(s_det)
+    torch.cuda.synchronize()
+    steps = 20
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    det_s = float(np.mean([a.elapsed_time(b) for a, b in det_events])) / 1e3
+    n = len(insts)
+    evals = n * 2 * S * params.dict_cap
+    mfma_flops = evals * 6 * (32 + 16) + n * 2 * S * 6 * 32 * 16
+    achieved = mfma_flops / det_s / 1e12
+    ser = {f"{s:g}dB": float(e.sum().item()) / (S * K) for s, e in zip(snrs, errs)}
+    out = {
+        "workload": ("realistic slot: K=6 users QPSK, 16 Rx antennas (2M=32), near-far [-6,0] dB, Rapp PA p=2 "
+                     "A_sat=1, SNR 5/10/15/20 dB (4 instances), 1024 pilots, 1048576 data symbols, W=32, "
+                     "sigma2=0.5, eps=0.05, mu=1, dictionary cap 1024; pipelined as the headline"),
+        "user_symbols_per_s": n * S * K / (elapsed / steps),
+        "ms_per_step": elapsed / steps * 1e3,
+        "ms_per_step_serialized": serial_ms,
+        "train_ms_4_instances": train_ms,
+        "detect_ms_one_launch_4_instances": det_s * 1e3,
+        "kernel_evals_per_s": evals / det_s,
+        "roofline": {"kernel": "detect_wide_batch_kernel", "bound": "mfma", "achieved": achieved,
+                     "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP16_MFMA_TFLOPS,
+                     "valu_frac_of_fp32_peak": evals * 16 / det_s / 1e12 / PEAK_FP32_VALU_TFLOPS},
+        "ser_gpu": ser,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle trains the 10 dB instance itself and detects a sample:
+        # its SER and decision mismatches against the GPU's on those symbols,
+        # and its time (best of 3 for detection) scaled to the step
+        log("[bench] slot: oracle training and sampled detection")
+        i10 = snrs.index(10.0)
+        inst = insts[i10]
+        p = O.APSMParams(sigma2=0.5, eps=0.05, mu=1.0, window=32, dict_cap=1024)
+        t0 = time.perf_counter()
+        f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, p)
+        t_train = time.perf_counter() - t0
+        rng = np.random.default_rng(7)
+        idx = np.unique(np.r_[0:256, S - 256:S, rng.integers(0, S, 1536)])
+        soft_ref = [None]
+
+        def det():
+            soft_ref[0] = O.detect_planar(f, inst.rx_data[idx])
+        t_det = best_of(det)
+        sr = soft_ref[0]
+        lab_ref = O.decide(sr, "qpsk")
+        near = O.boundary_distance(sr, "qpsk") < 1e-5
+        # the detection of the timed region's last step used the last trained set
+        hard_gpu = hard[i10].cpu().numpy()[idx]
+        soft_gpu = soft[i10].cpu().numpy()[idx].astype(np.float64)
+        diff = hard_gpu != lab_ref
+        t_step = n * (t_train + t_det / len(idx) * S)
+        out["oracle_sample"] = {
+            "what": f"the oracle's own training of the 10 dB instance and detection of {len(idx)} symbols",
+            "max_scaled_error": float(np.max(np.abs(soft_gpu - sr) / np.maximum(np.abs(sr), 1 / np.sqrt(2)))),
+            "decision_mismatch_outside_band": int(np.sum(diff & ~near)),
+            "decision_mismatch_inside_band": int(np.sum(diff & near)),
+            "ser_gpu_sample": float(np.mean(hard_gpu != inst.truth[idx])),
+            "ser_oracle_sample": float(np.mean(lab_ref != inst.truth[idx])),
+        }
+        out["cpu_baseline"] = {
+            "value": n * S * K / t_step, "unit": "user-symbols/s", "cores": blas_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle ({blas_threads()} BLAS threads of {os.cpu_count()} host cores): full training "
+                       f"of the 10 dB instance ({t_train:.2f} s) and detection of {len(idx)} of {S} symbols "
+                       f"(best of 3, {t_det:.2f} s), extrapolated linearly to {n} instances x {S} symbols"),
+        }
+    return out
+
+
+# ---------------------------------------------------- batched mixed shapes (C3)
+
+def run_batched_mixed(args, dev):
     import torch
     import synth
     import paper_2201_05024_amd as A
 
     n = synth.BATCH_INSTANCES
-    log(f"[bench] generating the batched workload ({n} detectors)")
+    log(f"[bench] mixed batch: generating {n} detectors")
     params = A.Params(eps=0.05, mu=1.0, window=32)
-    items, evals, syms, flops = [], 0, 0, 0
+    items, evals, syms = [], 0, 0
+    cu = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
     for i in range(n):
         spec, D = synth.spec_batch_mixed(i)
         inst = synth.make_instance(spec)
         K, M2, S = spec.K, 2 * spec.M, spec.S
         items.append(A.BatchItem(
-            model=A.Model(M2, K, D, dev, 0.5), rx_pilot=torch.from_numpy(inst.rx_pilot).to(dev),
-            sym_pilot=torch.from_numpy(inst.sym_pilot).to(dev), rx=torch.from_numpy(inst.rx_data).to(dev),
-            modulation=spec.modulation, soft=torch.empty((S, K, 2), dtype=torch.float32, device=dev),
-            hard=torch.empty((S, K), dtype=torch.uint8, device=dev),
-            truth=torch.from_numpy(inst.truth).to(dev), errors=torch.zeros(K, dtype=torch.int64, device=dev),
-            sigma2=0.5))
+            model=A.Model(M2, K, D, dev, 0.5), rx_pilot=cu(inst.rx_pilot), sym_pilot=cu(inst.sym_pilot),
+            rx=cu(inst.rx_data), modulation=spec.modulation,
+            soft=torch.empty((S, K, 2), dtype=torch.float32, device=dev),
+            hard=torch.empty((S, K), dtype=torch.uint8, device=dev), truth=cu(inst.truth),
+            errors=torch.zeros(K, dtype=torch.int64, device=dev), sigma2=0.5))
         evals += 2 * S * D
-        flops += 2 * S * D * (2 + 8 + 2 * K)
         syms += S * K
     batch = A.Batch(params, items)
     stream = torch.cuda.current_stream()
@@ -154,14 +563,6 @@ def run_batched(args, dev):
             it.errors.zero_()
         batch.train(stream).detect(stream)
 
-    def plain_step():
-        for it in items:
-            it.errors.zero_()
-            p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, dict_cap=it.model.dict_cap)
-            A.train(it.rx_pilot, it.sym_pilot, p, model=it.model, stream=stream)
-            A.detect(it.model, it.rx, modulation=it.modulation, truth=it.truth, soft=it.soft, hard=it.hard,
-                     errors=it.errors, stream=stream)
-
     def timed(fn, steps):
         fn()
         torch.cuda.synchronize()
@@ -171,41 +572,151 @@ def run_batched(args, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    log("[bench] batched form")
-    t_batched = timed(batched_step, args.batched_steps)
-    log("[bench] plain form")
-    t_plain = timed(plain_step, 2)
-    # the detection launch alone, with HIP events on its stream
+    t_batched = timed(batched_step, 5)
+    # the same step captured once in a HIP graph and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for it in items:
+            it.errors.zero_()
+        batch.train(side).detect(side)
+    torch.cuda.synchronize()
+    t_graph = timed(g.replay, 5)
     ev = []
-    for _ in range(args.batched_steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+    for _ in range(5):
+        e = cuda_events()
+        e[0].record(stream)
         batch.detect(stream)
-        e1.record(stream)
-        ev.append((e0, e1))
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+        e[1].record(stream)
+        ev.append(e)
+    e = cuda_events()
+    e[0].record(stream)
     batch.train(stream)
-    e1.record(stream)
+    e[1].record(stream)
     torch.cuda.synchronize()
     det_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
-    train_ms = e0.elapsed_time(e1)
-    achieved = flops / det_s / 1e12
-    return {
+    out = {
         "workload": (f"{n} detectors, K 2..8, 8/16/32 antennas, dictionaries 64..2048 (= pilots), "
                      "65536 vectors each, QPSK/16-QAM mixed, SNR 5..20 dB, W=32, sigma2=0.5"),
         "batched_user_symbols_per_s": syms / t_batched,
-        "plain_user_symbols_per_s": syms / t_plain,
-        "speedup_vs_plain": t_plain / t_batched,
         "ms_per_step_batched": t_batched * 1e3,
-        "ms_per_step_plain": t_plain * 1e3,
-        "train_ms_one_launch": train_ms,
-        "detect_ms_one_launch": det_s * 1e3,
+        "graph_replay_ms": t_graph * 1e3,
+        "train_ms_one_batch": e[0].elapsed_time(e[1]),
+        "detect_ms_one_batch": det_s * 1e3,
         "kernel_evals_per_s": evals / det_s,
-        "roofline": {"kernel": "detect_batch_kernel", "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None},
     }
+    if not args.no_plain:
+        def plain_detect():
+            for it in items:
+                A.detect(it.model, it.rx, modulation=it.modulation, truth=it.truth, soft=it.soft, hard=it.hard,
+                         errors=it.errors, stream=stream)
+
+        def plain_step():
+            for it in items:
+                it.errors.zero_()
+                p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, dict_cap=it.model.dict_cap)
+                A.train(it.rx_pilot, it.sym_pilot, p, model=it.model, stream=stream)
+            plain_detect()
+        t_plain = timed(plain_step, 1)
+        t_plain_det = timed(plain_detect, 2)
+        out.update({
+            "plain_user_symbols_per_s": syms / t_plain,
+            "ms_per_step_plain": t_plain * 1e3,
+            "speedup_vs_plain": t_plain / t_batched,
+            "detect_ms_plain": t_plain_det * 1e3,
+            "detect_speedup_vs_plain": t_plain_det / det_s,
+        })
+    return out
+
+
+# ------------------------------------------------ differentiable training (C4)
+
+def run_unrolled(dev):
+    import torch
+    import synth
+    import paper_2201_05024_amd as A
+
+    n, K, M, P, S, W = 64, 6, 16, 512, 4096, 32
+    log(f"[bench] unrolled: {n} instances")
+    insts = [synth.make_instance(synth.InstanceSpec(K=K, M=M, P=P, S=S, snr_db=10.0, seed=900 + i))
+             for i in range(n)]
+    data = [torch.from_numpy(np.stack([getattr(i, a) for i in insts])).to(dev)
+            for a in ("rx_pilot", "sym_pilot", "rx_data", "sym_data")]
+    theta = torch.tensor([0.7, 0.05, 1.0] + [1.0] * W, dtype=torch.float32, device=dev, requires_grad=True)
+
+    def fwd_bwd():
+        theta.grad = None
+        L = A.unrolled_loss(theta, *data, passes=20, ckpt_every=5)
+        L.backward()
+        return L
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    e = cuda_events(3)
+    e[0].record()
+    L = A.unrolled_loss(theta, *data, passes=20, ckpt_every=5)
+    e[1].record()
+    L.backward()
+    e[2].record()
+    torch.cuda.synchronize()
+    return {"workload": ("differentiable unrolled training: 64 instances x (K=6, 16 antennas, 512 pilots, 4096 "
+                         "validation symbols), W=32, 20 passes, checkpoint every 5; gradient w.r.t. sigma, eps, "
+                         "mu and 32 position weights"),
+            "forward_ms": e[0].elapsed_time(e[1]), "backward_ms": e[1].elapsed_time(e[2]),
+            "forward_backward_ms": e[0].elapsed_time(e[2]), "loss": float(L.detach())}
+
+
+# ---------------------------------------- small plain case (C1), paper shape (P0)
+
+def run_small(dev):
+    import torch
+    import synth
+    import paper_2201_05024_amd as A
+
+    cu = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    out = {}
+    inst = synth.make_instance(synth.spec_plain_small())
+    p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=16, dict_cap=256)
+    rxp, symp, rx, truth = cu(inst.rx_pilot), cu(inst.sym_pilot), cu(inst.rx_data), cu(inst.truth)
+    m = A.train(rxp, symp, p)
+    o = A.detect(m, rx, truth=truth)
+    b = A.Batch(p, [A.BatchItem(model=A.Model(16, 4, 256, dev, 0.5), rx_pilot=rxp, sym_pilot=symp, rx=rx,
+                                soft=torch.empty_like(o["soft"]), hard=torch.empty_like(o["hard"]), truth=truth,
+                                errors=torch.zeros(4, dtype=torch.int64, device=dev))])
+    b.train().detect()
+    torch.cuda.synchronize()
+
+    def lat(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        e = cuda_events()
+        e[0].record()
+        for _ in range(reps):
+            fn()
+        e[1].record()
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / reps * 1e3
+
+    out["small_plain"] = {
+        "workload": "K=4 QPSK, 8 antennas, 256 pilots, 2048 data symbols, W=16, cap 256, 10 dB",
+        "train_us": lat(lambda: A.train(rxp, symp, p, model=m)),
+        "detect_us": lat(lambda: A.detect(m, rx, truth=truth, soft=o["soft"], hard=o["hard"], errors=o["errors"])),
+        "batch_train_detect_us": lat(lambda: b.train().detect()),
+    }
+    inst = synth.make_instance(synth.spec_paper_shape())
+    p = A.Params(sigma2=0.05, eps=0.05, mu=1.0, window=20, dict_cap=2 * inst.spec.P)
+    rxp, symp, rx = cu(inst.rx_pilot), cu(inst.sym_pilot), cu(inst.rx_data)
+    m = A.train(rxp, symp, p)
+    o = A.detect(m, rx)
+    out["paper_shape"] = {
+        "workload": "6 users QPSK, 16 antennas, 685 pilots (dictionary 1370), 3840 data symbols, W=20, sigma2=0.05",
+        "train_ms": lat(lambda: A.train(rxp, symp, p, model=m), 5) / 1e3,
+        "detect_ms": lat(lambda: A.detect(m, rx, soft=o["soft"], hard=o["hard"])) / 1e3,
+        "paper_detect_ms_context": {"RTX 2060 Super": 1.25, "RTX 2080 Ti": 0.906, "Titan V": 0.403,
+                                    "source": "paper Table tab:optimization_results, Balanced implementation"},
+    }
+    return out
 
 
 def main():
@@ -216,7 +727,6 @@ def main():
         return 2
 
     import torch
-    import synth
     import paper_2201_05024_amd as A
 
     if not torch.cuda.is_available():
@@ -226,187 +736,27 @@ def main():
     torch.cuda.set_device(dev)
     A.library()  # fail loudly if the HIP library is missing
 
-    snrs = synth.SLOT_SNRS_DB
-    params = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, w_lin=0.5, w_gauss=0.5,
-                      dict_cap=1024)
-    log(f"[bench] generating {len(snrs)} slot instances")
-    insts = [synth.make_instance(synth.spec_slot(s)) for s in snrs]
-    K, M2, P, S = insts[0].spec.K, 2 * insts[0].spec.M, insts[0].spec.P, insts[0].spec.S
-    rx_p = torch.from_numpy(np.stack([i.rx_pilot for i in insts])).to(dev)
-    sym_p = torch.from_numpy(np.stack([i.sym_pilot for i in insts])).to(dev)
-    rx_d = [torch.from_numpy(i.rx_data).to(dev) for i in insts]
-    truth = [torch.from_numpy(i.truth).to(dev) for i in insts]
-    # Two model sets: in the pipelined schedule the detectors of step k are
-    # trained while the detection of step k - 1 runs on the other set.
-    models = [[A.Model(M2, K, params.dict_cap, dev, params.sigma2) for _ in insts] for _ in range(2)]
-    # each set is trained by one batch (kernel rows of the 4 pilot blocks in
-    # one data-parallel launch, then the 4 trainings in one launch)
-    tbatch = [A.Batch(params, [A.BatchItem(model=ms[i], rx_pilot=rx_p[i], sym_pilot=sym_p[i])
-                               for i in range(len(insts))]) for ms in models]
-
-    def train_set(k, stream):
-        tbatch[k].train(stream)
-    soft = [torch.empty((S, K, 2), dtype=torch.float32, device=dev) for _ in insts]
-    hard = [torch.empty((S, K), dtype=torch.uint8, device=dev) for _ in insts]
-    errs = [torch.zeros(K, dtype=torch.int64, device=dev) for _ in insts]
-    s_train = torch.cuda.Stream()
-    s_det = torch.cuda.Stream()
-    trained = [torch.cuda.Event(), torch.cuda.Event()]
-    detected = [torch.cuda.Event(), torch.cuda.Event()]
-    rows_ready = [torch.cuda.Event(), torch.cuda.Event()]
-    torch.cuda.synchronize()
-
-    det_events = []
-
-    def detect_set(ms, stream, record):
-        for e in errs:
-            e.zero_()
-        for i in range(len(insts)):
-            if record:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            A.detect(ms[i], rx_d[i], modulation="qpsk", truth=truth[i], soft=soft[i],
-                     hard=hard[i], errors=errs[i], stream=stream)
-            if record:
-                e1.record(stream)
-                det_events.append((e0, e1))
-
-    def step(k, record):
-        cur, prev = k % 2, (k + 1) % 2
-        if args.serial:
-            with torch.cuda.stream(s_det):
-                train_set(cur, s_det)
-                detect_set(models[cur], s_det, record)
-            return
-        # the kernel rows of step k's pilots (a short launch over the whole
-        # GPU) ahead of the detections on the detection stream; then the four
-        # trainings of step k (one launch) beside the detection of step k - 1
-        with torch.cuda.stream(s_det):
-            tbatch[cur].kernel_rows(s_det)
-            rows_ready[cur].record(s_det)
-        with torch.cuda.stream(s_train):
-            s_train.wait_event(detected[cur])
-            s_train.wait_event(rows_ready[cur])
-            tbatch[cur].train_prepared(s_train)
-            trained[cur].record(s_train)
-        with torch.cuda.stream(s_det):
-            s_det.wait_event(trained[prev])
-            detect_set(models[prev], s_det, record)
-            detected[prev].record(s_det)
-
-    log(f"[bench] warmup {args.warmup}")
-    # the set detected first in the timed region is trained here
-    with torch.cuda.stream(s_train):
-        train_set(1, s_train)
-        trained[1].record(s_train)
-    for k in range(args.warmup):
-        step(k, False)
-    torch.cuda.synchronize()
-
-    # training alone, for the report
-    t_ev0, t_ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_ev0.record(s_train)
-    train_set(0, s_train)
-    t_ev1.record(s_train)
-    torch.cuda.synchronize()
-    train_ms = t_ev0.elapsed_time(t_ev1)
-    # the serialized step (train, then detect) for the report
-    t0 = time.perf_counter()
-    for _ in range(3):
-        with torch.cuda.stream(s_det):
-            train_set(0, s_det)
-            detect_set(models[0], s_det, False)
-    torch.cuda.synchronize()
-    serial_ms = (time.perf_counter() - t0) / 3 * 1e3
-    # re-arm the pipeline: set 1 trained, set 0 free
-    with torch.cuda.stream(s_train):
-        train_set(1, s_train)
-        trained[1].record(s_train)
-    with torch.cuda.stream(s_det):
-        detected[0].record(s_det)
-    torch.cuda.synchronize()
-
-    log(f"[bench] timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k, True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log("[bench] timed region done")
-
-    det_ms = [a.elapsed_time(b) for a, b in det_events]
-    det_avg_s = float(np.mean(det_ms)) / 1e3
-    n_inst = len(insts)
-    sym_per_step = n_inst * S * K
-    value = sym_per_step * args.steps / elapsed
-    D = params.dict_cap
-    S_r = 2 * S
-    evals_per_launch = S_r * D
-    # VALU work per kernel evaluation: one FMA for the exponent argument, one
-    # exp2 (4 issue slots = 8 flop-equivalents) and K coefficient FMAs.
-    valu_flops_per_eval = 2 + 8 + 2 * K
-    valu_flops = evals_per_launch * valu_flops_per_eval
-    achieved_tflops = valu_flops / det_avg_s / 1e12
-    mfma_tflops = evals_per_launch * 2 * M2 / det_avg_s / 1e12
-    ser = {f"{s:g}dB": float(e.sum().item()) / (S * K) for s, e in zip(snrs, errs)}
-
+    head = run_large(args, dev)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head.pop("value"),
         "unit": "user-symbols/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded Rayleigh channel, near-far, Rapp PA, AWGN)",
-        "config": {
-            "workload": ("realistic slot: K=6 users QPSK, 16 Rx antennas (2M=32), near-far "
-                         "[-6,0] dB, Rapp PA p=2 A_sat=1, SNR 5/10/15/20 dB (4 instances), "
-                         "1024 pilots, 1048576 data symbols, W=32, sigma2=0.5, eps=0.05, "
-                         "mu=1, dictionary cap 1024"),
-            "instances_per_step": n_inst,
-            "data_symbols": S,
-            "pilots": P,
-        },
-        "roofline": {
-            "kernel": "detect_f16_kernel<32,6>",
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": PEAK_FP32_VALU_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-            "traffic": measured_traffic(),
-            "per_launch": {"real_vectors": S_r, "dictionary": D,
-                           "kernel_evals": evals_per_launch,
-                           "valu_flops_per_eval": valu_flops_per_eval,
-                           "avg_ms": det_avg_s * 1e3, "launches_timed": len(det_ms),
-                           "inner_product_tflops_on_mfma": mfma_tflops},
-        },
-        "detect_only": {
-            "user_symbols_per_s": S * K / det_avg_s,
-            "kernel_evals_per_s": evals_per_launch / det_avg_s,
-        },
-        "train_ms_4_instances": train_ms,
-        "schedule": ("serial: train then detect within each step" if args.serial else
-                     "pipelined: the kernel rows of step k's pilots (one launch) precede the detections "
-                     "on the detection stream; the trainings of step k (one launch, 4 CUs) run beside "
-                     "the detection of step k-1 on a second stream; every step trains 4 detectors and "
-                     "detects 4 x 1048576 symbols"),
-        "ms_per_step_serialized": serial_ms,
-        "train_steps_per_instance": 2 * P,
-        "ser_gpu": ser,
+        "dtype": "f32 (FP32 inputs, outputs and accumulation; both inner-product blocks as 3-term split-fp16 MFMA)",
+        "data": "synthetic (seeded Rayleigh channel, Rapp PA, AWGN), generated on the device",
     }
-    if not args.no_cpu_baseline:
-        log("[bench] timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(lambda snr, S: synth.spec_slot(snr, S=S), 10.0, params,
-                                           S, n_inst)
-    if not args.no_batched:
-        out["batched"] = run_batched(args, dev)
+    out.update(head)
+    if not args.headline_only:
+        out["slot"] = run_slot(args, dev)
+        out["batched_mixed"] = run_batched_mixed(args, dev)
+        out["unrolled"] = run_unrolled(dev)
+        out.update(run_small(dev))
     if args.copy_calibration:
         n = 64 << 20
         a = torch.ones(n, dtype=torch.float32, device=dev)
