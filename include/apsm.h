@@ -116,11 +116,11 @@ typedef struct apsm_params {
  *                         training steps done, status flags (APSM_FLAG_*)};
  *                         detection only ORs APSM_FLAG_DETECT_NONFINITE into
  *                         the flags word.
- *  packed apsm_model_packed_bytes(M2, K, dict_cap) bytes: the same filter
- *         re-laid out for the detection kernels (written by apsm_train and by
- *         apsm_model_pack, read by apsm_detect).  Required when that size is
- *         nonzero (2M <= 64 and K <= 8); may be NULL otherwise.  It does not
- *         depend on sigma2.
+ *  packed apsm_model_packed_bytes(M2, K, dict_cap) bytes (required): the
+ *         same filter re-laid out for the detection kernels (written by
+ *         apsm_train and by apsm_model_pack, read by apsm_detect); for
+ *         2M <= 64 and K <= 8 it holds the layouts of both detection kernels.
+ *         It does not depend on sigma2.
  * sigma2 travels with the call (apsm_detect) rather than in this struct. */
 typedef struct apsm_model {
   int32_t M2;
@@ -236,9 +236,9 @@ typedef struct apsm_batch apsm_batch_t;   /* opaque host object */
 int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* items, int n,
                       apsm_batch_t** out);
 
-/* Bytes of device workspace the batch needs: job tables, the work-item list
- * of detection, two claim counters and the training kernel rows (for each
- * detector with dict_cap <= 4096: 2P x (dict_cap + window) floats, the
+/* Bytes of device workspace the batch needs: job tables, the work-item
+ * lists of detection, claim counters and the training kernel rows (for each
+ * detector with dict_cap <= 8192: 2P x (dict_cap + window) floats, the
  * Gaussian kernel values of every pilot step against the dictionary entries
  * it sees, computed by one data-parallel launch before training). */
 size_t apsm_batch_workspace_bytes(const apsm_batch_t* batch);
@@ -250,13 +250,28 @@ size_t apsm_batch_workspace_bytes(const apsm_batch_t* batch);
  * workspace is NULL, too small or misaligned. */
 int apsm_batch_bind(apsm_batch_t* batch, void* workspace, size_t bytes, void* stream);
 
-/* Time the launch forms of batched detection on this batch (persistent
- * workgroups claiming tiles from a counter, or one workgroup per tile) and
- * keep the faster one for this batch and for later batches of the same
- * shape mix (the choice is cached per process).  Runs the batch's detection
- * several times: soft and hard outputs are overwritten and err_count
- * accumulates those runs, so zero err_count afterwards.  Synchronous. */
+/* Autotune batched detection on this GPU and record the choices in the
+ * library's tuning cache (see apsm_tune_save): (1) for every shape class in
+ * the batch that both detection kernels hold (2M <= 64 and K <= 8; class =
+ * 2M padded to 16/32/64 and K), time the split-FP16 kernel (coefficient sums
+ * on VALU) against the two-contraction kernel (coefficient sums on the matrix
+ * cores) on the class's largest detector, keep the faster for the class (this
+ * batch's jobs move to that kernel's launch; later batches and apsm_detect
+ * calls of the class use it too); (2) time the launch forms (persistent
+ * workgroups claiming work items from a counter, or one workgroup per item)
+ * and keep the faster for this shape mix.  Runs detections several times:
+ * soft and hard outputs are overwritten and err_count accumulates those
+ * runs, so zero err_count afterwards.  Synchronous; not while capturing. */
 int apsm_batch_tune(apsm_batch_t* batch, void* stream);
+
+/* Set the launch form of this batch's detection (overrides the tuned or
+ * default choice): persistent != 0 for a grid of workgroups that claim work
+ * items until none is left, sized to occupy `cus` compute units (cus <= 0:
+ * all of them; fewer leave whole CUs free for kernels on other streams, such
+ * as the next batch's training), 0 for one workgroup per work item.  Outputs
+ * do not depend on the form.  Host only; takes effect at the next
+ * apsm_batch_detect. */
+int apsm_batch_set_form(apsm_batch_t* batch, int persistent, int cus);
 
 /* Train every detector of the batch (same results as apsm_train per item)
  * and pack the models; asynchronous on `stream`.  The same as
@@ -359,8 +374,18 @@ int apsm_train_noalloc(const apsm_params_t* params, int M2, int K, int P,
  * flags word host_state[3] is nonzero, APSM_OK otherwise. */
 int apsm_get_status(const apsm_model_t* model, int32_t* host_state);
 
+/* Tuning cache: the choices of apsm_batch_tune, keyed by GPU architecture
+ * name, HIP runtime version and shape class (detection kernel) or batch
+ * shape mix (launch form).  apsm_tune_save writes the cache to `path` (HOST
+ * string) as a JSON object of string pairs; apsm_tune_load merges such a
+ * file into it (entries measured on another architecture or runtime are kept
+ * but never match).  APSM_ERR_INVALID_ARG if the file cannot be written, read
+ * or parsed (nothing is merged then).  Thread-safe. */
+int apsm_tune_save(const char* path);
+int apsm_tune_load(const char* path);
+
 /* Release what the library keeps on the host between calls: the launch-form
- * and tile choices cached by apsm_batch_tune.  Device memory is not touched
+ * and kernel choices cached by apsm_batch_tune (the tuning cache).  Device memory is not touched
  * (the library holds none besides its static scratch array).  Safe to call at
  * any time from one thread while no other library call runs; later calls
  * work as after loading the library. */

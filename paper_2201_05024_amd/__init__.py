@@ -13,7 +13,7 @@ from dataclasses import dataclass
 from typing import Optional, Sequence
 
 __all__ = ["Params", "Model", "train", "train_noalloc", "train_batched", "detect", "Batch", "BatchItem", "APSMError",
-           "unrolled_loss", "APSMUnrolled", "library", "shutdown", "LIB_PATH", "MOD_NONE", "MOD_QPSK",
+           "unrolled_loss", "APSMUnrolled", "library", "shutdown", "tune_save", "tune_load", "LIB_PATH", "MOD_NONE", "MOD_QPSK",
            "MOD_QAM16", "ERR_WORKSPACE", "ERR_NONFINITE", "FLAG_TRAIN_NONFINITE", "FLAG_DETECT_NONFINITE"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapsm.so")
@@ -106,6 +106,8 @@ def library() -> ctypes.CDLL:
         L.apsm_batch_train_prepared.restype = i32
         L.apsm_batch_detect.argtypes = [vp, vp]
         L.apsm_batch_detect.restype = i32
+        L.apsm_batch_set_form.argtypes = [vp, i32, i32]
+        L.apsm_batch_set_form.restype = i32
         L.apsm_batch_destroy.argtypes = [vp]
         L.apsm_batch_destroy.restype = None
         L.apsm_unrolled_workspace_bytes.argtypes = [ctypes.POINTER(_CUnrolled)]
@@ -125,6 +127,10 @@ def library() -> ctypes.CDLL:
         L.apsm_train_noalloc.argtypes = [ctypes.POINTER(_CParams), i32, i32, i32, vp, vp,
                                          ctypes.POINTER(_CModel), vp]
         L.apsm_train_noalloc.restype = i32
+        L.apsm_tune_save.argtypes = [ctypes.c_char_p]
+        L.apsm_tune_save.restype = i32
+        L.apsm_tune_load.argtypes = [ctypes.c_char_p]
+        L.apsm_tune_load.restype = i32
         L.apsm_shutdown.argtypes = []
         L.apsm_shutdown.restype = None
         _lib = L
@@ -217,6 +223,20 @@ class Model:
         if rc and rc != ERR_NONFINITE:
             raise APSMError(rc, "apsm_get_status")
         return {"size": out[0], "head": out[1], "steps": out[2], "flags": out[3]}
+
+
+def tune_save(path: str) -> None:
+    """Write the tuning cache (apsm_tune_save) as JSON."""
+    rc = library().apsm_tune_save(os.fsencode(path))
+    if rc:
+        raise APSMError(rc, "apsm_tune_save")
+
+
+def tune_load(path: str) -> None:
+    """Merge a saved tuning cache (apsm_tune_load)."""
+    rc = library().apsm_tune_load(os.fsencode(path))
+    if rc:
+        raise APSMError(rc, "apsm_tune_load")
 
 
 def shutdown() -> None:
@@ -405,6 +425,14 @@ class Batch:
         rc = library().apsm_batch_tune(self._h, _stream_handle(stream))
         if rc:
             raise APSMError(rc, "apsm_batch_tune")
+        return self
+
+    def set_form(self, persistent: bool, cus: int = 0) -> "Batch":
+        """Persistent (claiming, on `cus` CUs; 0 = all) or
+        one-workgroup-per-item detection launches."""
+        rc = library().apsm_batch_set_form(self._h, int(bool(persistent)), int(cus))
+        if rc:
+            raise APSMError(rc, "apsm_batch_set_form")
         return self
 
     def train(self, stream=None) -> "Batch":

@@ -145,19 +145,27 @@ struct PackJob {
 // largest capacity among them.
 hipError_t launch_pack_model_batch(const PackJob* jobs, int n, int max_cap, hipStream_t stream);
 
-// Two-contraction detection (detect_wide.h): every shape the split-FP16
-// kernels do not hold (2M > 64 or K > 8).  Packing many models in one
+// Two-contraction detection (detect_wide.h).  Packing many models in one
 // launch pair (max_threads: the largest wide_pack_threads of the jobs) and
-// detection of many jobs in one launch over (job, item) pairs, item i of a
-// job covering received vectors 128 i .. 128 i + 127 (persistent form with
-// ctr as for launch_detect_batch).
-bool detect_is_wide(int M2, int K);
+// detection of many jobs of one padded width (variant = wide_detect_variant)
+// in one launch over (job, item) pairs, item i of a job covering received
+// vectors 128 i .. 128 i + 127 (persistent form with ctr as for
+// launch_detect_batch).
+// Detection kernels: kDetectF16 (split-FP16 distance block, coefficients on
+// VALU; 2M <= 64 and K <= 8) and kDetectWide (both contractions on the
+// matrix cores; every shape).  Shapes both kernels hold ("dual") carry both
+// packed images, the two-contraction one at wide_offset.
+enum { kDetectF16 = 0, kDetectWide = 1 };
+bool detect_dual(int M2, int K);
+int detect_default_kernel(int M2, int K);
+size_t wide_offset(int M2, int K, int cap);
+hipError_t launch_detect_with(const DetectArgs& a, int kernel, hipStream_t stream);
 int wide_pack_threads(int M2, int cap);
 int wide_detect_variant(int M2);
 int wide_detect_items(int S);
 hipError_t launch_pack_wide_batch(const PackJob* jobs, int n, int max_threads, hipStream_t stream);
 hipError_t launch_detect_wide_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr, int grid,
-                                    hipStream_t stream);
+                                    int variant, hipStream_t stream);
 
 // Batched detection.  Jobs whose shape has detect_batch_variant >= 0 run in
 // one launch over a global sequence of work items, item i being tile
@@ -169,9 +177,19 @@ hipError_t launch_detect_wide_batch(const DetJob* jobs, const int2* items, int n
 // zero between launches).
 int detect_batch_variant(int M2, int K);
 int detect_tiles(int S);
-int detect_batch_grid();
+int device_cus();
 hipError_t launch_detect_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr,
                                int grid, hipStream_t stream);
+
+// Tuning cache (tune.cpp): host-side, mutex-guarded, keyed by the GPU's
+// architecture name and HIP runtime version.  detect_kernel_for gives the
+// kernel recorded for a dual shape class (2M padded as the split-FP16
+// kernel pads it, K), else detect_default_kernel.
+int detect_kernel_for(int M2, int K);
+void tune_set_kernel(int M2, int K, int kernel);
+bool tune_get_form(uint64_t signature, bool* persistent);
+void tune_set_form(uint64_t signature, bool persistent);
+void tune_clear();
 
 // Unrolled training and its adjoint.  Instance b's part of the workspace
 // starts at ws + b * inst_bytes; the off_* are byte offsets inside it.

@@ -41,13 +41,15 @@ struct apsm_batch {
   std::vector<apsm::DetJob> djobs;
   std::vector<int2> ditems;
   std::vector<apsm::DetJob> wjobs;             // two-contraction detection
-  std::vector<int2> witems;
+  std::vector<int2> witems;                    // grouped by padded width (one launch each)
+  int wbegin[4] = {0, 0, 0, 0};                // items of width class c: [wbegin[c], wbegin[c + 1])
   std::vector<int> train_plain;      // items trained with their own launch
   size_t off_t = 0, off_rj = 0, off_ri = 0, off_p = 0, off_pw = 0, off_d = 0, off_i = 0, off_wd = 0, off_wi = 0,
          off_c = 0, off_rows = 0, bytes = 0;
   unsigned char* ws = nullptr;       // bound workspace (device)
   bool persistent = true;
-  int grid = 0, grid_wide = 0;
+  int cus = 0;                       // CUs the persistent grids occupy (0: all)
+  int grid = 0;                      // CUs of the device
   uint64_t signature = 0;
 };
 
@@ -129,15 +131,76 @@ uint64_t signature_of(const std::vector<apsm_batch_item_t>& items) {
   return h;
 }
 
-std::mutex g_tune_mutex;
-std::map<uint64_t, bool> g_tuned;   // signature -> persistent form chosen
-
-bool tuned_choice(uint64_t sig, bool* persistent) {
-  std::lock_guard<std::mutex> lock(g_tune_mutex);
-  auto f = g_tuned.find(sig);
-  if (f == g_tuned.end()) return false;
-  *persistent = f->second;
-  return true;
+// Detection jobs and work items of the two kernels, from the kernel choice
+// of each item's shape class (tuned, else the default); each list ordered
+// by the cost of one work item (dictionary stages times per-entry work),
+// most expensive first.
+void assign_detection(apsm_batch& b) {
+  const int n = (int)b.items.size();
+  b.djobs.clear();
+  b.ditems.clear();
+  b.wjobs.clear();
+  b.witems.clear();
+  std::vector<int> det, wdet;
+  for (int i = 0; i < n; ++i) {
+    const auto& it = b.items[i];
+    if (it.S <= 0) continue;
+    (detect_kernel_for(it.model.M2, it.model.K) == kDetectF16 ? det : wdet).push_back(i);
+  }
+  std::vector<double> dcost(n, 0.0);
+  for (int i : det) {
+    const auto& it = b.items[i];
+    const double D = std::min<double>(2.0 * it.P, it.model.dict_cap);
+    dcost[i] = (std::ceil(D / 64.0) + 0.25) * (it.model.K + 6 + it.model.M2 / 16.0);
+  }
+  for (int i : wdet) {
+    const auto& it = b.items[i];
+    const double D = std::min<double>(2.0 * it.P, it.model.dict_cap);
+    dcost[i] = (std::ceil(D / 64.0) + 0.25) * (6.0 * it.model.M2 / 32.0 + 1.0);
+  }
+  auto by_cost = [&](int a, int c) { return dcost[a] > dcost[c]; };
+  std::stable_sort(det.begin(), det.end(), by_cost);
+  // two-contraction jobs grouped by padded width (one launch per width), by cost within
+  auto wvar = [&](int i) { return wide_detect_variant(b.items[i].model.M2); };
+  std::stable_sort(wdet.begin(), wdet.end(), [&](int a, int c) {
+    return wvar(a) != wvar(c) ? wvar(a) < wvar(c) : dcost[a] > dcost[c];
+  });
+  auto det_job = [&](const apsm_batch_item_t& it, int variant, size_t packed_off) {
+    DetJob d{};
+    d.packed = static_cast<const unsigned char*>(it.model.packed) + packed_off;
+    d.w = it.model.w;
+    d.state = it.model.state;
+    d.flags = it.model.state + 3;
+    d.rx = it.rx;
+    d.soft = it.soft;
+    d.hard = it.hard;
+    d.truth = it.truth;
+    d.err = reinterpret_cast<unsigned long long*>(it.err_count);
+    d.cap = it.model.dict_cap;
+    d.M2 = it.model.M2;
+    d.K = it.model.K;
+    d.S = it.S;
+    d.modulation = it.modulation;
+    d.c2 = kLog2e / (2.0f * it.sigma2);
+    d.variant = variant;
+    return d;
+  };
+  for (int i : det) {
+    const auto& it = b.items[i];
+    const int job = (int)b.djobs.size();
+    b.djobs.push_back(det_job(it, detect_batch_variant(it.model.M2, it.model.K), 0));
+    const int tiles = detect_tiles(it.S);
+    for (int t = 0; t < tiles; ++t) b.ditems.push_back(make_int2(job, t));
+  }
+  for (int c = 0; c < 4; ++c) b.wbegin[c] = 0;
+  for (int i : wdet) {
+    const auto& it = b.items[i];
+    const int job = (int)b.wjobs.size();
+    b.wjobs.push_back(det_job(it, wvar(i), wide_offset(it.model.M2, it.model.K, it.model.dict_cap)));
+    const int nit = wide_detect_items(it.S);
+    for (int t = 0; t < nit; ++t) b.witems.push_back(make_int2(job, t));
+    for (int c = wvar(i) + 1; c < 4; ++c) b.wbegin[c] = (int)b.witems.size();
+  }
 }
 
 void plan(apsm_batch& b, const apsm_params_t* p) {
@@ -203,11 +266,9 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
     b.train_lds = std::max(b.train_lds, train_lds_bytes(p->window, j.M2, j.K, j.cap));
   }
 
-  // packing and detection
-  std::vector<int> det, wdet;
+  // packing: dual shapes get both packed images
   for (int i = 0; i < n; ++i) {
     const auto& it = b.items[i];
-    const bool wide = detect_is_wide(it.model.M2, it.model.K);
     PackJob pj{};
     pj.dict = it.model.dict;
     pj.alpha = it.model.alpha;
@@ -217,65 +278,30 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
     pj.cap = it.model.dict_cap;
     pj.M2 = it.model.M2;
     pj.K = it.model.K;
-    pj.variant = wide ? -1 : detect_batch_variant(it.model.M2, it.model.K);
-    if (wide) {
-      b.pwjobs.push_back(pj);
-      b.pack_wide_threads = std::max(b.pack_wide_threads, wide_pack_threads(pj.M2, pj.cap));
-    } else {
+    if (detect_dual(pj.M2, pj.K)) {
+      pj.variant = detect_batch_variant(pj.M2, pj.K);
       b.pjobs.push_back(pj);
       b.pack_max_cap = std::max(b.pack_max_cap, pj.cap);
     }
-    if (it.S > 0) (wide ? wdet : det).push_back(i);
+    pj.variant = -1;
+    pj.packed += wide_offset(pj.M2, pj.K, pj.cap);
+    b.pwjobs.push_back(pj);
+    b.pack_wide_threads = std::max(b.pack_wide_threads, wide_pack_threads(pj.M2, pj.cap));
   }
-  // cost of one work item: dictionary stages times per-entry work
-  std::vector<double> dcost(n, 0.0);
-  for (int i : det) {
-    const auto& it = b.items[i];
-    const double D = std::min<double>(2.0 * it.P, it.model.dict_cap);
-    dcost[i] = (std::ceil(D / 64.0) + 0.25) * (it.model.K + 6 + it.model.M2 / 16.0);
+
+  // detection tables sized for either kernel choice of every dual shape, so
+  // that tuning can move jobs between the two launches in place
+  size_t max_dj = 0, max_di = 0, max_wj = 0, max_wi = 0;
+  for (const auto& it : b.items) {
+    if (it.S <= 0) continue;
+    if (detect_dual(it.model.M2, it.model.K)) {
+      ++max_dj;
+      max_di += detect_tiles(it.S);
+    }
+    ++max_wj;
+    max_wi += wide_detect_items(it.S);
   }
-  for (int i : wdet) {
-    const auto& it = b.items[i];
-    const double D = std::min<double>(2.0 * it.P, it.model.dict_cap);
-    dcost[i] = (std::ceil(D / 64.0) + 0.25) * (6.0 * it.model.M2 / 32.0 + 1.0);
-  }
-  auto by_cost = [&](int a, int c) { return dcost[a] > dcost[c]; };
-  std::stable_sort(det.begin(), det.end(), by_cost);
-  std::stable_sort(wdet.begin(), wdet.end(), by_cost);
-  auto det_job = [&](const apsm_batch_item_t& it, int variant) {
-    DetJob d{};
-    d.packed = static_cast<const unsigned char*>(it.model.packed);
-    d.w = it.model.w;
-    d.state = it.model.state;
-    d.flags = it.model.state + 3;
-    d.rx = it.rx;
-    d.soft = it.soft;
-    d.hard = it.hard;
-    d.truth = it.truth;
-    d.err = reinterpret_cast<unsigned long long*>(it.err_count);
-    d.cap = it.model.dict_cap;
-    d.M2 = it.model.M2;
-    d.K = it.model.K;
-    d.S = it.S;
-    d.modulation = it.modulation;
-    d.c2 = kLog2e / (2.0f * it.sigma2);
-    d.variant = variant;
-    return d;
-  };
-  for (int i : det) {
-    const auto& it = b.items[i];
-    const int job = (int)b.djobs.size();
-    b.djobs.push_back(det_job(it, detect_batch_variant(it.model.M2, it.model.K)));
-    const int tiles = detect_tiles(it.S);
-    for (int t = 0; t < tiles; ++t) b.ditems.push_back(make_int2(job, t));
-  }
-  for (int i : wdet) {
-    const auto& it = b.items[i];
-    const int job = (int)b.wjobs.size();
-    b.wjobs.push_back(det_job(it, wide_detect_variant(it.model.M2)));
-    const int nit = wide_detect_items(it.S);
-    for (int t = 0; t < nit; ++t) b.witems.push_back(make_int2(job, t));
-  }
+  assign_detection(b);
 
   b.off_t = 0;
   b.off_rj = align256(b.off_t + b.tjobs.size() * sizeof(TrainJob));
@@ -283,15 +309,15 @@ void plan(apsm_batch& b, const apsm_params_t* p) {
   b.off_p = align256(b.off_ri + b.ritems.size() * sizeof(int4));
   b.off_pw = align256(b.off_p + b.pjobs.size() * sizeof(PackJob));
   b.off_d = align256(b.off_pw + b.pwjobs.size() * sizeof(PackJob));
-  b.off_i = align256(b.off_d + b.djobs.size() * sizeof(DetJob));
-  b.off_wd = align256(b.off_i + b.ditems.size() * sizeof(int2));
-  b.off_wi = align256(b.off_wd + b.wjobs.size() * sizeof(DetJob));
-  b.off_c = align256(b.off_wi + b.witems.size() * sizeof(int2));
+  b.off_i = align256(b.off_d + max_dj * sizeof(DetJob));
+  b.off_wd = align256(b.off_i + max_di * sizeof(int2));
+  b.off_wi = align256(b.off_wd + max_wj * sizeof(DetJob));
+  b.off_c = align256(b.off_wi + max_wi * sizeof(int2));
   b.off_rows = b.off_c + 256;                 // tables end here (the bound image)
   b.bytes = b.off_rows + b.rows_floats * sizeof(float);
   b.signature = signature_of(b.items);
   bool pers = true;
-  if (tuned_choice(b.signature, &pers)) b.persistent = pers;
+  if (tune_get_form(b.signature, &pers)) b.persistent = pers;
 }
 
 template <class T>
@@ -299,18 +325,22 @@ const T* at(const apsm_batch* b, size_t off) {
   return reinterpret_cast<const T*>(b->ws + off);
 }
 
-// The two detection launches; the persistent forms use the counter pairs at
-// off_c (split-FP16) and off_c + 8 (two-contraction).
+// The detection launches: split-FP16 (counter pair at off_c) and one
+// two-contraction launch per padded width class c (pair at off_c + 8 + 8 c).
 int run_detect(const apsm_batch* b, bool persistent, hipStream_t stream) {
   unsigned int* ctr = reinterpret_cast<unsigned int*>(b->ws + b->off_c);
-  if (!b->witems.empty()) {
-    hipError_t e = launch_detect_wide_batch(at<DetJob>(b, b->off_wd), at<int2>(b, b->off_wi), (int)b->witems.size(),
-                                            persistent ? ctr + 2 : nullptr, b->grid_wide, stream);
+  const int cus = b->cus > 0 && b->cus < b->grid ? b->cus : b->grid;
+  for (int c = 0; c < 3; ++c) {
+    const int n = b->wbegin[c + 1] - b->wbegin[c];
+    if (n <= 0) continue;
+    // workgroups per CU: two of the 32-wide specialisation, one of the wider
+    hipError_t e = launch_detect_wide_batch(at<DetJob>(b, b->off_wd), at<int2>(b, b->off_wi) + b->wbegin[c], n,
+                                            persistent ? ctr + 2 + 2 * c : nullptr, (c == 0 ? 2 : 1) * cus, c, stream);
     if (e != hipSuccess) return hip_status(e);
   }
   if (!b->ditems.empty()) {
     hipError_t e = launch_detect_batch(at<DetJob>(b, b->off_d), at<int2>(b, b->off_i), (int)b->ditems.size(),
-                                       persistent ? ctr : nullptr, b->grid, stream);
+                                       persistent ? ctr : nullptr, 2 * cus, stream);
     if (e != hipSuccess) return hip_status(e);
   }
   return APSM_OK;
@@ -371,8 +401,7 @@ int apsm_batch_bind(apsm_batch_t* b, void* workspace, size_t bytes, void* stream
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_status(e);
   b->ws = static_cast<unsigned char*>(workspace);
-  b->grid = detect_batch_grid();
-  b->grid_wide = b->grid / 2;        // one 512-thread workgroup per CU
+  b->grid = device_cus();
   return APSM_OK;
 }
 
@@ -434,38 +463,79 @@ int apsm_batch_tune(apsm_batch_t* b, void* stream) {
     (void)hipEventDestroy(e0);
     return hip_status(hipGetLastError());
   }
-  float best[2] = {0.0f, 0.0f};
   int rc = APSM_OK;
-  for (int form = 0; form < 2 && rc == APSM_OK; ++form) {
-    const bool pers = form == 1;
-    rc = run_detect(b, pers, s);                           // warm-up
-    float tmin = 0.0f;
+  // best of three timed runs after one warm-up
+  auto time_ms = [&](auto&& run, float* best) {
+    rc = run();
     for (int rep = 0; rep < 3 && rc == APSM_OK; ++rep) {
       hipError_t e = hipEventRecord(e0, s);
-      if (e == hipSuccess) rc = run_detect(b, pers, s);
+      if (e == hipSuccess) rc = run();
       if (rc == APSM_OK && e == hipSuccess) e = hipEventRecord(e1, s);
       if (rc == APSM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;
       if (rc == APSM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e != hipSuccess) rc = hip_status(e);
-      if (rep == 0 || ms < tmin) tmin = ms;
+      if (rep == 0 || ms < *best) *best = ms;
     }
-    best[form] = tmin;
+  };
+
+  // 1. the detection kernel of every shape class both kernels hold (2M as the
+  //    split-FP16 kernel pads it, K): both timed on the class's largest
+  //    detector of this batch, the faster recorded in the tuning cache
+  std::map<std::pair<int, int>, int> classes;       // (padded 2M, K) -> item
+  for (int i = 0; i < (int)b->items.size(); ++i) {
+    const auto& it = b->items[i];
+    if (it.S <= 0 || !detect_dual(it.model.M2, it.model.K)) continue;
+    const int m2p = it.model.M2 <= 16 ? 16 : it.model.M2 <= 32 ? 32 : 64;
+    auto f = classes.find({m2p, it.model.K});
+    if (f == classes.end() || b->items[f->second].S < it.S) classes[{m2p, it.model.K}] = i;
   }
+  for (const auto& cl : classes) {
+    if (rc != APSM_OK) break;
+    const auto& it = b->items[cl.second];
+    const DetectArgs a = detect_args(&it.model, it.sigma2, it.S, it.rx, it.soft, it.hard, it.modulation, it.truth,
+                                     it.err_count);
+    float t[2] = {0.0f, 0.0f};
+    for (int k = 0; k < 2 && rc == APSM_OK; ++k)
+      time_ms([&] { return hip_status(launch_detect_with(a, k == 0 ? kDetectF16 : kDetectWide, s)); }, &t[k]);
+    if (rc == APSM_OK) tune_set_kernel(it.model.M2, it.model.K, t[0] < t[1] ? kDetectF16 : kDetectWide);
+  }
+  if (rc == APSM_OK && !classes.empty()) {
+    // move the jobs to the launches of their chosen kernels (tables rewritten in place)
+    assign_detection(*b);
+    const std::pair<size_t, const void*> parts[4] = {
+        {b->djobs.size() * sizeof(DetJob), b->djobs.data()}, {b->ditems.size() * sizeof(int2), b->ditems.data()},
+        {b->wjobs.size() * sizeof(DetJob), b->wjobs.data()}, {b->witems.size() * sizeof(int2), b->witems.data()}};
+    const size_t offs[4] = {b->off_d, b->off_i, b->off_wd, b->off_wi};
+    for (int q = 0; q < 4 && rc == APSM_OK; ++q) {
+      if (parts[q].first == 0) continue;
+      hipError_t e = hipMemcpyAsync(b->ws + offs[q], parts[q].second, parts[q].first, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = hip_status(e);
+    }
+  }
+
+  // 2. the launch form: persistent workgroups claiming items, or one
+  //    workgroup per item
+  float best[2] = {0.0f, 0.0f};
+  for (int form = 0; form < 2 && rc == APSM_OK; ++form)
+    time_ms([&] { return run_detect(b, form == 1, s); }, &best[form]);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != APSM_OK) return rc;
   b->persistent = best[1] <= best[0];
-  std::lock_guard<std::mutex> lock(g_tune_mutex);
-  g_tuned[b->signature] = b->persistent;
+  tune_set_form(b->signature, b->persistent);
+  return APSM_OK;
+}
+
+int apsm_batch_set_form(apsm_batch_t* b, int persistent, int cus) {
+  if (!b) return APSM_ERR_INVALID_ARG;
+  b->persistent = persistent != 0;
+  b->cus = cus > 0 ? cus : 0;
   return APSM_OK;
 }
 
 void apsm_batch_destroy(apsm_batch_t* b) { delete b; }
 
-void apsm_shutdown(void) {
-  std::lock_guard<std::mutex> lock(g_tune_mutex);
-  g_tuned.clear();
-}
 
 }  // extern "C"

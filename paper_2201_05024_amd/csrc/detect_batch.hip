@@ -121,14 +121,16 @@ int detect_batch_variant(int M2, int K) {
 
 int detect_tiles(int S) { return (S + f16::kWaves * 16 - 1) / (f16::kWaves * 16); }
 
-// Two workgroups per CU: the specialisations use up to 256 VGPRs (two waves
-// per SIMD) and two copies of the largest LDS footprint fit a CU.
-int detect_batch_grid() {
+// Compute units of the current device (256 if it cannot be queried).  The
+// persistent form of this kernel runs two workgroups per CU: the
+// specialisations use up to 256 VGPRs (two waves per SIMD) and two copies of
+// the largest LDS footprint fit a CU.
+int device_cus() {
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 512;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    return 512;
-  return 2 * cus;
+    return 256;
+  return cus;
 }
 
 hipError_t launch_detect_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr, int grid,

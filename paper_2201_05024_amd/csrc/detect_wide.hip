@@ -209,21 +209,6 @@ __device__ __forceinline__ DetJob load_job(const DetJob* p) {
   return d;
 }
 
-constexpr int kBatchLds = tile_lds_bytes<128>();
-static_assert(tile_lds_bytes<64>() <= kBatchLds && tile_lds_bytes<32>() <= kBatchLds, "LDS bound");
-
-__device__ __forceinline__ void run_item(const DetJob* jobs, const int2* items, int item, unsigned char* lds,
-                                         unsigned int* werr) {
-  const int jx = uni(items[item].x), tile = uni(items[item].y);
-  const DetJob d = load_job(jobs + jx);
-  switch (d.variant) {
-    case 0: detect_wide_tile<32>(d, d.packed, tile, lds, werr); break;
-    case 1: detect_wide_tile<64>(d, d.packed, tile, lds, werr); break;
-    case 2: detect_wide_tile<128>(d, d.packed, tile, lds, werr); break;
-    default: break;
-  }
-}
-
 __device__ __forceinline__ int claim(unsigned int* ctr, int* s_item) {
   if (threadIdx.x == 0) *s_item = (int)atomicAdd(ctr, 1u);
   __syncthreads();
@@ -232,20 +217,32 @@ __device__ __forceinline__ int claim(unsigned int* ctr, int* s_item) {
   return item;
 }
 
-// Persistent form (ctr != null): workgroups claim items in list order; the
-// last one to finish restores the counters to zero.  Plain form: workgroup
-// b runs item b.
-__global__ __launch_bounds__(kThreads) void detect_wide_batch_kernel(const DetJob* jobs, const int2* items, int n_items,
-                                                                     unsigned int* ctr) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[kBatchLds];
+// Many detectors of one padded width in one launch.  Persistent form (ctr
+// != null): workgroups claim items in list order; the last one to finish
+// restores the counters to zero.  Plain form: workgroup b runs item b.
+// Waves per SIMD the register budget is sized for: four for the 32-wide
+// specialisation (two workgroups per CU, at most 128 VGPRs), two for the
+// wider ones.
+template <int M2P>
+constexpr int batch_waves_per_simd() { return M2P == 32 ? 4 : 2; }
+
+template <int M2P>
+__global__ __launch_bounds__(kThreads, batch_waves_per_simd<M2P>()) void detect_wide_batch_kernel(
+    const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[tile_lds_bytes<M2P>()];
   __shared__ unsigned int werr[16];
   __shared__ int s_item;
-  if (ctr == nullptr) {
-    run_item(jobs, items, blockIdx.x, lds, werr);
-    return;
+  const bool persistent = ctr != nullptr;
+  // one call site of the tile body (the loop runs once in the plain form)
+  int item = persistent ? claim(ctr, &s_item) : (int)blockIdx.x;
+  while (item < n_items) {
+    const int jx = uni(items[item].x), tile = uni(items[item].y);
+    const DetJob d = load_job(jobs + jx);
+    detect_wide_tile<M2P>(d, d.packed, tile, lds, werr);
+    if (!persistent) break;
+    item = claim(ctr, &s_item);
   }
-  for (int item = claim(ctr, &s_item); item < n_items; item = claim(ctr, &s_item))
-    run_item(jobs, items, item, lds, werr);
+  if (!persistent) return;
   if (threadIdx.x == 0) {
     __threadfence();
     const unsigned int done = atomicAdd(ctr + 1, 1u);
@@ -298,11 +295,14 @@ int wide_detect_variant(int M2) { const int p = wide::m2p_wide(M2); return p == 
 int wide_detect_items(int S) { return (int)(((long long)2 * S + wide::kVecPerItem - 1) / wide::kVecPerItem); }
 
 hipError_t launch_detect_wide_batch(const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr, int grid,
-                                    hipStream_t stream) {
+                                    int variant, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   const int blocks = ctr ? grid : n_items;
-  hipLaunchKernelGGL(wide::detect_wide_batch_kernel, dim3(blocks), dim3(wide::kThreads), 0, stream, jobs, items,
-                     n_items, ctr);
+  switch (variant) {
+    case 0: hipLaunchKernelGGL(wide::detect_wide_batch_kernel<32>, dim3(blocks), dim3(wide::kThreads), 0, stream, jobs, items, n_items, ctr); break;
+    case 1: hipLaunchKernelGGL(wide::detect_wide_batch_kernel<64>, dim3(blocks), dim3(wide::kThreads), 0, stream, jobs, items, n_items, ctr); break;
+    default: hipLaunchKernelGGL(wide::detect_wide_batch_kernel<128>, dim3(blocks), dim3(wide::kThreads), 0, stream, jobs, items, n_items, ctr); break;
+  }
   return hipGetLastError();
 }
 

@@ -133,18 +133,31 @@ def test_detect_rejects_bad_args():
 def test_packed_bytes():
     L = A.library()
     L.apsm_model_packed_bytes.restype = ctypes.c_size_t
-    # 2M = 32 -> rows of (2*32 + 8) halves, K = 6 -> (8 + 4) floats per entry, cap 1000 -> 1024 rows
-    assert L.apsm_model_packed_bytes(32, 6, 1000) == 64 + 1024 * (72 * 2 + 12 * 4)
+    def wide(m2p, cap):
+        # two-contraction layout: 256-byte header, the linear weights (2M/32 x
+        # 2 KiB), stages of 64 entries: rows of (2 * 2M + 8) halves, 4 KiB of
+        # coefficients, 1 KiB of norms
+        return 256 + m2p // 32 * 2048 + -(-cap // 64) * (64 * (2 * m2p + 8) * 2 + 4096 + 1024)
+
+    def f16(m2p, k4, cap):
+        # split-FP16 layout: 64-byte header, rows padded to 128 entries of
+        # (2 * 2M + 8) halves and (K4 + 4) floats; the wide image follows at
+        # the next multiple of 256 bytes
+        return (64 + -(-cap // 128) * 128 * ((2 * m2p + 8) * 2 + (k4 + 4) * 4) + 255) // 256 * 256
+
+    # 2M = 32, K = 6: both layouts (2M = 32 -> rows of (2*32 + 8) halves, K = 6 -> (8 + 4) floats per entry)
+    assert L.apsm_model_packed_bytes(32, 6, 1000) == f16(32, 8, 1000) + wide(32, 1000)
+    assert f16(32, 8, 1000) == (64 + 1024 * (72 * 2 + 12 * 4) + 255) // 256 * 256
     # two-contraction layout (2M > 64 or K > 8): 256-byte header, the linear
     # weights (2M/32 x 2 KiB), stages of 64 entries: rows of (2 * 2M + 8)
     # halves, 4 KiB of coefficients, 1 KiB of norms
     assert L.apsm_model_packed_bytes(128, 16, 1000) == 256 + 4 * 2048 + 16 * (64 * 528 + 4096 + 1024)
-    assert L.apsm_model_packed_bytes(128, 3, 64) == 256 + 4 * 2048 + 1 * (64 * 528 + 4096 + 1024)
+    assert L.apsm_model_packed_bytes(128, 3, 64) == wide(128, 64)         # 2M > 64: one layout
     assert L.apsm_model_packed_bytes(32, 9, 65) == 256 + 1 * 2048 + 2 * (64 * 144 + 4096 + 1024)
     assert L.apsm_model_packed_bytes(20, 12, 10) == L.apsm_model_packed_bytes(32, 16, 64)
     assert L.apsm_model_packed_bytes(66, 1, 10) == L.apsm_model_packed_bytes(128, 16, 64)
-    # 2M = 40 runs with the 64-wide layout: rows of 2*64+8 halves, K4 + 4 floats each
-    assert L.apsm_model_packed_bytes(40, 2, 40) == 64 + 128 * ((2 * 64 + 8) * 2 + (4 + 4) * 4)
+    # 2M = 40 runs with the 64-wide layouts: rows of 2*64+8 halves, K4 + 4 floats each
+    assert L.apsm_model_packed_bytes(40, 2, 40) == f16(64, 4, 40) + wide(64, 40)
     for m2 in range(34, 65, 2):
         assert L.apsm_model_packed_bytes(m2, 5, 300) == L.apsm_model_packed_bytes(64, 5, 300), m2
     for m2 in range(18, 33, 2):
@@ -314,3 +327,34 @@ def test_unrolled_workspace_and_validation():
     assert L.apsm_unrolled_forward(ctypes.byref(u), *args, 256, nbytes, None, None) == 1    # no loss
     assert L.apsm_unrolled_forward(ctypes.byref(u), None, 1, 1, 1, 1, 256, nbytes, 1, None) == 1
     assert L.apsm_unrolled_backward(ctypes.byref(u), *args, 256, nbytes, None, None, None) == 1
+
+
+@needs_lib
+def test_tune_cache_save_and_load(tmp_path):
+    """The tuning cache round-trips through its JSON file; a malformed file
+    or an unknown choice is rejected without merging anything."""
+    import json
+    A.shutdown()
+    empty = tmp_path / "empty.json"
+    A.tune_save(str(empty))
+    assert json.loads(empty.read_text()) == {}
+    entries = {"gfx950|hip70000000|detect|m2p32|k6": "wide", "gfx950|hip70000000|detect|m2p16|k4": "f16",
+               "gfx950|hip70000000|form|00000000deadbeef": "persistent"}
+    src = tmp_path / "cache.json"
+    src.write_text(json.dumps(entries, indent=1))
+    A.tune_load(str(src))
+    out = tmp_path / "out.json"
+    A.tune_save(str(out))
+    assert json.loads(out.read_text()) == entries
+    for bad in ('{"a": "fastest"}', '{"a": "wide"', "not json", '{"a" "wide"}'):
+        f = tmp_path / "bad.json"
+        f.write_text(bad)
+        with pytest.raises(A.APSMError):
+            A.tune_load(str(f))
+    A.tune_save(str(out))
+    assert json.loads(out.read_text()) == entries          # nothing merged from the bad files
+    with pytest.raises(A.APSMError):
+        A.tune_load(str(tmp_path / "missing.json"))
+    A.shutdown()                                            # releases the cache
+    A.tune_save(str(out))
+    assert json.loads(out.read_text()) == {}
