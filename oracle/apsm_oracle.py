@@ -140,6 +140,11 @@ class APSMParams:
     w_gauss: float = 0.5
     dict_cap: Optional[int] = None          # None: the dictionary grows without bound
     pos_weights: Optional[np.ndarray] = None  # omega[0..W-1], omega[0] for j = n
+    # "position": q_j from the position weights (uniform 1/|J_n| without them);
+    # "violation": per user k, q_kj = d_kj / sum_{i in J_n} d_ki with d_kj =
+    # max(|f_n(r_j) - b_kj| - eps, 0) the distance of f_n(r_j) to its slab
+    # (0 for every member when none is violated)
+    weight_mode: str = "position"
 
 
 class Filter:
@@ -230,19 +235,28 @@ def set_weights(n: int, J: range, p: APSMParams) -> dict:
 
 
 class Trainer:
-    """Windowed parallel hyperslab projections (eqn:apsm), one step at a time."""
+    """Windowed parallel hyperslab projections (eqn:apsm), one step at a time.
+
+    f0: the initial filter (Sec. II-D leaves f_0 arbitrary; default f_0 = 0).
+    n0: global index of the first sample of R when continuing a filter that
+    has already seen n0 samples: the samples enter its dictionary as
+    n0, n0 + 1, .. (FIFO eviction continues across the boundary), while the
+    window J_n starts afresh inside R."""
 
     def __init__(self, R: np.ndarray, B: np.ndarray, p: APSMParams,
-                 f0: Optional[Filter] = None):
+                 f0: Optional[Filter] = None, n0: int = 0):
         self.R = np.asarray(R, dtype=np.float64)
         self.B = np.asarray(B, dtype=np.float64)
         self.p = p
         if p.dict_cap is not None and p.dict_cap < p.window:
             raise ValueError("dictionary cap must be at least the window size")
+        if p.weight_mode not in ("position", "violation"):
+            raise ValueError(p.weight_mode)
         T, M2 = self.R.shape
         K = self.B.shape[1]
         self.f = f0.copy() if f0 is not None else Filter(K, M2, p.sigma2)
         self.n = 0
+        self.n0 = n0
 
     def step(self):
         """One step n: returns (J_n, e, beta) for inspection."""
@@ -252,7 +266,7 @@ class Trainer:
         # the oldest Gaussian term leaves first.
         if p.dict_cap is not None and len(f.dict_vec) == p.dict_cap:
             f.evict_oldest()
-        f.append(r_n, n)
+        f.append(r_n, self.n0 + n)
 
         J = window(n, p.window)
         q = set_weights(n, J, p)
@@ -264,11 +278,19 @@ class Trainer:
         for j in J:
             kjj = kappa_sum(self.R[j], self.R[j], p.sigma2, p.w_lin, p.w_gauss)
             bet[j] = np.array([beta(e[j][k], self.B[j, k], p.eps, kjj) for k in range(f.K)])
+        if p.weight_mode == "violation":
+            # q_kj proportional to the distance of f_n(r_j) to slab C_kj (the
+            # paper leaves the weights free to prioritise sets adaptively)
+            dist = {j: np.maximum(np.abs(e[j] - self.B[j]) - p.eps, 0.0) for j in J}
+            tot = sum(dist.values())
+            qk = {j: np.divide(dist[j], tot, out=np.zeros(f.K), where=tot > 0) for j in J}
+        else:
+            qk = {j: np.full(f.K, q[j]) for j in J}
         for j in J:
-            c = p.mu * q[j] * bet[j]                       # [K]
+            c = p.mu * qk[j] * bet[j]                      # [K]
             # P_{C_j} adds beta_j (wL kappa_L(r_j, .) + wG kappa_G(r_j, .)).
             f.w += np.outer(c * p.w_lin, self.R[j])
-            f.alpha[f.slot_of(j)] += c * p.w_gauss
+            f.alpha[f.slot_of(self.n0 + j)] += c * p.w_gauss
         self.n += 1
         return J, e, bet
 
@@ -284,13 +306,72 @@ def train(R: np.ndarray, B: np.ndarray, p: APSMParams,
 
 
 def train_from_pilots(rx_pilot_planar: np.ndarray, sym_pilot_pairs: np.ndarray,
-                      p: APSMParams) -> Filter:
-    """Convenience: planar float arrays as stored for the library -> Filter."""
+                      p: APSMParams, f0: Optional[Filter] = None, n0: int = 0) -> Filter:
+    """Planar float arrays as stored for the library -> Filter: training from
+    f0 (default f_0 = 0) whose dictionary has seen n0 samples before."""
     rx = _planar_to_complex(rx_pilot_planar)
     sym = np.asarray(sym_pilot_pairs, dtype=np.float64)
     sym = sym[..., 0] + 1j * sym[..., 1]
     R, B = training_sequence(rx, sym)
-    return train(R, B, p)
+    tr = Trainer(R, B, p, f0=f0, n0=n0)
+    for _ in range(len(R)):
+        tr.step()
+    return tr.f
+
+
+# --------------------------------------------------------------------------
+# Initialisation by a conventional linear filter when channel information is
+# available (Sec. I; Sec. II-D: f_0 in eqn:apsm is arbitrary, and may be a
+# linear filter of H_L).  The linear filter is the textbook MMSE receiver
+# (a reading: the paper names no particular one).
+# --------------------------------------------------------------------------
+
+def linear_mmse(H: np.ndarray, n0: float) -> np.ndarray:
+    """Linear MMSE receive filters for the model r = H x + n of Sec. II-C with
+    unit-power symbols and noise CN(0, n0 I): U = H (H^H H + n0 I)^{-1}, user
+    k's estimate u_k^H r (column k of U)."""
+    H = np.asarray(H, dtype=np.complex128)
+    K = H.shape[1]
+    G = H.conj().T @ H + n0 * np.eye(K)
+    return H @ np.linalg.inv(G)
+
+
+def filter_from_linear(U: np.ndarray, sigma2: float) -> Filter:
+    """The filter whose detection g_k(r) = f_k(r1) + i f_k(r2) equals u_k^H r:
+    f_k(x) = w_k^T x with w_k = [Re u_k; Im u_k] (real split of Sec. II-D), an
+    empty Gaussian dictionary."""
+    U = np.asarray(U, dtype=np.complex128)
+    M, K = U.shape
+    f = Filter(K, 2 * M, sigma2)
+    f.w = np.concatenate([U.real.T, U.imag.T], axis=1)
+    return f
+
+
+# --------------------------------------------------------------------------
+# Decision-directed tracking (Sec. II-E: the filter keeps adapting on the
+# detected data symbols)
+# --------------------------------------------------------------------------
+
+def decided_symbols(soft: np.ndarray, modulation: str) -> np.ndarray:
+    """soft [..., 2] -> the decided constellation points, complex."""
+    lv = axis_levels(modulation)
+    return lv[slice_axis(soft[..., 0], modulation)] + 1j * lv[slice_axis(soft[..., 1], modulation)]
+
+
+def decision_directed(f: Filter, rx_planar: np.ndarray, modulation: str, p: APSMParams,
+                      n0: int) -> tuple:
+    """One block of tracking: detect the block with the frozen filter f
+    (Sec. III-B), take the slicer's decisions as the targets b, and continue
+    the iteration over the block's real training sequence (its samples enter
+    the dictionary as n0, n0 + 1, ..; the window starts afresh).  Returns
+    (the updated filter, the soft outputs the decisions came from)."""
+    soft = detect_planar(f, rx_planar)
+    bhat = decided_symbols(soft, modulation)
+    R, B = training_sequence(_planar_to_complex(rx_planar), bhat)
+    tr = Trainer(R, B, p, f0=f, n0=n0)
+    for _ in range(len(R)):
+        tr.step()
+    return tr.f, soft
 
 
 def _planar_to_complex(x):
