@@ -74,6 +74,21 @@ extern "C" {
 #define APSM_MOD_QPSK   2
 #define APSM_MOD_QAM16  4
 
+/* Initial filter of a training (apsm_params_t.init). */
+#define APSM_INIT_ZERO      0      /* f_0 = 0: the model is reset                                */
+#define APSM_INIT_LINEAR    1      /* f_0 = the model's linear part w (e.g. from apsm_linear_mmse),
+                                      Gaussian dictionary emptied (needs w_lin > 0)              */
+#define APSM_INIT_CONTINUE  2      /* continue the model as it is: its dictionary ring, Gaussian
+                                      and linear coefficients and sample count (state[2]) carry on,
+                                      the window J_n starts afresh with the new samples (needs
+                                      w_lin > 0; one-detector training entry points only)        */
+
+/* Set weights q_j of a training step (apsm_params_t.weights). */
+#define APSM_WEIGHTS_POSITION   0  /* uniform 1/|J_n|, or the position weights pos_weights      */
+#define APSM_WEIGHTS_VIOLATION  1  /* per user k, q_kj proportional to member j's distance
+                                      max(|f_n(r_j) - b_kj| - eps, 0) to its slab (0 for all when
+                                      none is violated); pos_weights must be NULL               */
+
 /* Design parameters of the iteration (HOST struct).
  *  sigma2      Gaussian kernel width sigma^2 > 0 (Sec. II-A).
  *  eps         hyperslab half-width eps >= 0 (eqn:convex_set).
@@ -87,9 +102,14 @@ extern "C" {
  *              the oldest Gaussian term is dropped first (its linear part
  *              stays).  dict_cap >= 2P gives the paper's ever-growing
  *              dictionary exactly.
+ *  init        APSM_INIT_*: the initial filter f_0 (Sec. II-D leaves it arbitrary;
+ *              Sec. I: a conventional linear filter when channel information
+ *              is available) or the continuation of a trained model.
  *  pos_weights HOST pointer to `window` positive floats omega (omega[0] for the
  *              newest set j = n), q_j = omega[n-j] / sum_{i in J_n} omega[n-i];
- *              NULL for uniform q_j = 1/|J_n| (eqn:apsm's weights, Sec. II-D). */
+ *              NULL for uniform q_j = 1/|J_n| (eqn:apsm's weights, Sec. II-D).
+ *  weights     APSM_WEIGHTS_*: position weights, or weights proportional to the
+ *              slab violation (Sec. II-D: the q_j may prioritise sets adaptively). */
 typedef struct apsm_params {
   float sigma2;
   float eps;
@@ -98,8 +118,10 @@ typedef struct apsm_params {
   float w_gauss;
   int32_t window;
   int32_t dict_cap;
-  int32_t reserved;           /* must be 0 */
+  int32_t init;
   const float* pos_weights;
+  int32_t weights;
+  int32_t reserved;           /* must be 0 */
 } apsm_params_t;
 
 /* A trained detector: the whole filter state (Sec. III-B: dictionary plus
@@ -144,7 +166,8 @@ size_t apsm_model_packed_bytes(int M2, int K, int dict_cap);
 int apsm_model_pack(const apsm_model_t* model, void* stream);
 
 /* Training (Sec. II-D eqn:apsm with eqn:beta; Sec. III-B training phase).
- * Resets `model` to f_0 = 0, runs the 2P steps n = 0..2P-1 of the real
+ * Starts from the initial filter params->init names (f_0 = 0 resets the
+ * model), runs the 2P steps n = 0..2P-1 of the real
  * training sequence r_{2t} = r1(t), r_{2t+1} = r2(t), b_{k,2t} = Re b_k(t),
  * b_{k,2t+1} = Im b_k(t), and packs the result (apsm_model_pack).
  *  params     HOST, see apsm_params_t.
@@ -187,6 +210,39 @@ int apsm_train_batched(const apsm_params_t* params, int M2, int K, int P, int n_
 int apsm_detect(const apsm_model_t* model, float sigma2, int S,
                 const float* rx, float* soft, uint8_t* hard, int modulation,
                 const uint8_t* truth, int64_t* err_count, void* stream);
+
+/* Linear MMSE receive filters from channel estimates, as the linear start
+ * f_0 of a training (APSM_INIT_LINEAR; Sec. I: initialisation by a
+ * conventional linear filter when channel information is available).  For
+ * each of n_inst instances with channel H in C^{M x K} (column k: user k's
+ * channel, including its power and any known scale of the received
+ * vectors) and noise variance n0 per antenna:
+ *     U = H (H^H H + n0 I)^{-1},   w_k = [Re u_k; Im u_k],
+ * so that w_k . r1 + i w_k . r2 = u_k^H r (the real split of Sec. II-D).
+ *  h      [n_inst][K][M2] DEVICE: column k of H as [Re h_k; Im h_k].
+ *  n0     >= 0 (0 needs H of full column rank).
+ *  w      [n_inst][K][M2] DEVICE output (e.g. model.w of a detector).
+ * Asynchronous on `stream`. */
+int apsm_linear_mmse(const float* h, float n0, int M2, int K, int n_inst, float* w, void* stream);
+
+/* Decision-directed tracking (Sec. II-E, remark on focusing on detection:
+ * gradual channel changes are tracked by running the iteration on the data
+ * symbols).  For a block of S received vectors: detect them with the frozen
+ * filter (as apsm_detect), replace the soft outputs by the decided
+ * constellation points, then continue the training of `model` over the
+ * block's real training sequence with those decisions as the targets (as
+ * apsm_train with APSM_INIT_CONTINUE: the dictionary ring continues, the
+ * window starts afresh) and repack the model.
+ *  params     HOST; its init field is not used (tracking always continues);
+ *             needs w_lin > 0 and dict_cap == model->dict_cap.
+ *  modulation APSM_MOD_QPSK or APSM_MOD_QAM16.
+ *  decided    [S][K][2] DEVICE output: the decided symbols (Re, Im) the block
+ *             was tracked on.
+ *  hard, truth, err_count  optional, as for apsm_detect (decisions of the
+ *             frozen filter, before the block's update).
+ * Asynchronous on `stream`. */
+int apsm_track(const apsm_params_t* params, const apsm_model_t* model, int S, const float* rx, int modulation,
+               float* decided, uint8_t* hard, const uint8_t* truth, int64_t* err_count, void* stream);
 
 /* ---- batches of detectors with different shapes ----------------------
  * Many independent detectors (each its own user count K, input dimension

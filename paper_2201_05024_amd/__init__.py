@@ -13,7 +13,7 @@ from dataclasses import dataclass
 from typing import Optional, Sequence
 
 __all__ = ["Params", "Model", "train", "train_noalloc", "train_batched", "detect", "Batch", "BatchItem", "APSMError",
-           "unrolled_loss", "APSMUnrolled", "library", "shutdown", "tune_save", "tune_load", "LIB_PATH", "MOD_NONE", "MOD_QPSK",
+           "unrolled_loss", "APSMUnrolled", "library", "shutdown", "tune_save", "tune_load", "linear_mmse", "track", "LIB_PATH", "MOD_NONE", "MOD_QPSK",
            "MOD_QAM16", "ERR_WORKSPACE", "ERR_NONFINITE", "FLAG_TRAIN_NONFINITE", "FLAG_DETECT_NONFINITE"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapsm.so")
@@ -38,7 +38,12 @@ class _CParams(ctypes.Structure):
     _fields_ = [("sigma2", ctypes.c_float), ("eps", ctypes.c_float), ("mu", ctypes.c_float),
                 ("w_lin", ctypes.c_float), ("w_gauss", ctypes.c_float),
                 ("window", ctypes.c_int32), ("dict_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("pos_weights", ctypes.POINTER(ctypes.c_float))]
+                ("init", ctypes.c_int32), ("pos_weights", ctypes.POINTER(ctypes.c_float)),
+                ("weights", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+INIT = {"zero": 0, "linear": 1, "continue": 2}
+WEIGHTS = {"position": 0, "violation": 1}
 
 
 class _CModel(ctypes.Structure):
@@ -131,6 +136,11 @@ def library() -> ctypes.CDLL:
         L.apsm_tune_save.restype = i32
         L.apsm_tune_load.argtypes = [ctypes.c_char_p]
         L.apsm_tune_load.restype = i32
+        L.apsm_linear_mmse.argtypes = [vp, f32, i32, i32, i32, vp, vp]
+        L.apsm_linear_mmse.restype = i32
+        L.apsm_track.argtypes = [ctypes.POINTER(_CParams), ctypes.POINTER(_CModel), i32, vp, i32, vp, vp, vp,
+                                 vp, vp]
+        L.apsm_track.restype = i32
         L.apsm_shutdown.argtypes = []
         L.apsm_shutdown.restype = None
         _lib = L
@@ -151,6 +161,8 @@ class Params:
     w_gauss: float = 0.5
     dict_cap: int = 256
     pos_weights: Optional[Sequence[float]] = None
+    init: str = "zero"               # "zero" | "linear" (f_0 = the model's w) | "continue"
+    weights: str = "position"        # "position" | "violation"
 
     def _c(self):
         pw = None
@@ -159,7 +171,7 @@ class Params:
             keep = (ctypes.c_float * len(self.pos_weights))(*[float(x) for x in self.pos_weights])
             pw = ctypes.cast(keep, ctypes.POINTER(ctypes.c_float))
         p = _CParams(self.sigma2, self.eps, self.mu, self.w_lin, self.w_gauss,
-                     int(self.window), int(self.dict_cap), 0, pw)
+                     int(self.window), int(self.dict_cap), INIT[self.init], pw, WEIGHTS[self.weights], 0)
         return p, keep
 
 
@@ -237,6 +249,51 @@ def tune_load(path: str) -> None:
     rc = library().apsm_tune_load(os.fsencode(path))
     if rc:
         raise APSMError(rc, "apsm_tune_load")
+
+
+def linear_mmse(h, n0: float, w=None, stream=None):
+    """Linear MMSE filters from channel estimates (apsm_linear_mmse):
+    h [n][K][2M] or [K][2M] float32 device tensor (column k of H as
+    [Re h_k; Im h_k]) -> w of the same shape, w_k = [Re u_k; Im u_k]."""
+    torch = _torch()
+    squeeze = h.dim() == 2
+    hh = h.unsqueeze(0) if squeeze else h
+    n, K, M2 = hh.shape
+    _check(hh, torch.float32, (n, K, M2), "h")
+    if w is None:
+        w = torch.empty_like(hh)
+    else:
+        w = w.view(n, K, M2)
+    rc = library().apsm_linear_mmse(hh.data_ptr(), float(n0), M2, K, n, w.data_ptr(), _stream_handle(stream))
+    if rc:
+        raise APSMError(rc, "apsm_linear_mmse")
+    return w[0] if squeeze else w
+
+
+def track(model: "Model", rx, params: Params, modulation="qpsk", truth=None, decided=None, hard=None,
+          errors=None, stream=None):
+    """Decision-directed tracking of one block (apsm_track): detect rx
+    [S][2M] with the frozen model, continue its training on the decided
+    symbols.  Returns {'decided', 'hard', 'errors'} (decisions of the frozen
+    model)."""
+    torch = _torch()
+    S = rx.shape[0]
+    _check(rx, torch.float32, (S, model.M2), "rx")
+    mod = _MODS[modulation]
+    dev = rx.device
+    if decided is None:
+        decided = torch.empty((S, model.K, 2), dtype=torch.float32, device=dev)
+    if truth is not None and errors is None:
+        errors = torch.zeros(model.K, dtype=torch.int64, device=dev)
+    p, keep = params._c()
+    m = model._c()
+    ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+    rc = library().apsm_track(ctypes.byref(p), ctypes.byref(m), S, rx.data_ptr(), mod, ptr(decided), ptr(hard),
+                              ptr(truth), ptr(errors), _stream_handle(stream))
+    del keep
+    if rc:
+        raise APSMError(rc, "apsm_track")
+    return {"decided": decided, "hard": hard, "errors": errors}
 
 
 def shutdown() -> None:

@@ -39,6 +39,11 @@ int check_params(const apsm_params_t* p) {
       p->w_gauss < 0.0f || (p->w_lin == 0.0f && p->w_gauss == 0.0f))
     return APSM_ERR_INVALID_ARG;
   if (p->reserved != 0 || p->window < 1) return APSM_ERR_INVALID_ARG;
+  if (p->init != APSM_INIT_ZERO && p->init != APSM_INIT_LINEAR && p->init != APSM_INIT_CONTINUE)
+    return APSM_ERR_INVALID_ARG;
+  if (p->init != APSM_INIT_ZERO && !(p->w_lin > 0.0f)) return APSM_ERR_INVALID_ARG;   // w = wL v
+  if (p->weights != APSM_WEIGHTS_POSITION && p->weights != APSM_WEIGHTS_VIOLATION) return APSM_ERR_INVALID_ARG;
+  if (p->weights == APSM_WEIGHTS_VIOLATION && p->pos_weights) return APSM_ERR_INVALID_ARG;
   if (p->window > APSM_MAX_WINDOW) return APSM_ERR_UNSUPPORTED;
   if (p->dict_cap < p->window) return APSM_ERR_INVALID_ARG;
   if (p->pos_weights) {
@@ -54,6 +59,8 @@ void fill_common(const apsm_params_t* p, TrainCommon& cm) {
   cm.mu = p->mu;
   cm.wl = p->w_lin;
   cm.wg = p->w_gauss;
+  cm.init = p->init;
+  cm.weights = p->weights;
   for (int i = 0; i < APSM_MAX_WINDOW; ++i) cm.omega[i] = 1.0f;
   if (p->pos_weights)
     for (int i = 0; i < p->window; ++i) cm.omega[i] = p->pos_weights[i];
@@ -122,11 +129,10 @@ const char* apsm_last_hip_error(void) { return g_last_hip_error.c_str(); }
 
 }  // extern "C"
 
-namespace {
-using namespace apsm;
+namespace apsm {
 
-// Shared by apsm_train and apsm_train_batched: every check happens before the
-// first launch.
+// Shared by apsm_train, apsm_train_batched and apsm_track: every check
+// happens before the first launch.
 int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const float* rx_pilot,
                const float* sym_pilot, const apsm_model_t* models, void* stream) {
   if (int rc = check_params(p)) return rc;
@@ -172,7 +178,9 @@ int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const f
   return APSM_OK;
 }
 
-}  // namespace
+}  // namespace apsm
+
+using namespace apsm;
 
 extern "C" {
 

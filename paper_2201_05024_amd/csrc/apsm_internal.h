@@ -16,10 +16,16 @@ constexpr float kLog2e = 1.4426950408889634f;
 // per-instance pointers fit the kernel-argument block.
 constexpr int kMaxTrainBatch = 32;
 
+// Initial filter and set weights of a training (apsm_params_t.init, .weights).
+enum { kInitZero = APSM_INIT_ZERO, kInitLinear = APSM_INIT_LINEAR, kInitContinue = APSM_INIT_CONTINUE };
+enum { kWeightsPosition = APSM_WEIGHTS_POSITION, kWeightsViolation = APSM_WEIGHTS_VIOLATION };
+
 // Parameters shared by every detector of a training launch.
 struct TrainCommon {
   int W;                  // window size
   float eps, mu, wl, wg;
+  int init;               // kInit*: f_0 = 0, the model's linear part, or the whole model continued
+  int weights;            // kWeights*: position weights (uniform by default) or violation weights
   float omega[APSM_MAX_WINDOW];   // position weights, omega[0] for j = n
 };
 
@@ -221,5 +227,9 @@ int check_detect_args(int M2, int K, float sigma2, int S, const float* rx, float
                       int modulation, const uint8_t* truth, int64_t* err_count);
 DetectArgs detect_args(const apsm_model_t* model, float sigma2, int S, const float* rx, float* soft,
                        uint8_t* hard, int modulation, const uint8_t* truth, int64_t* err_count);
+// apsm_train / apsm_train_batched after the argument checks of the public
+// entry points: n_inst detectors of one shape, pilots contiguous per detector.
+int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const float* rx_pilot,
+               const float* sym_pilot, const apsm_model_t* models, void* stream);
 
 }  // namespace apsm

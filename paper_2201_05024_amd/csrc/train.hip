@@ -137,13 +137,15 @@ struct Lds {
   float* aev;    // [KP]     coefficients of the evicted entry
   float* omega;  // [W]      position weights
   float* qs;     // [W+1]    mu / (omega_0 + .. + omega_{L-1}) for |J_n| = L
+  float* vb;     // [W][KP]  beta of the current step (violation weights)
+  float* vd;     // [W][KP]  slab distances of the current step (violation weights)
   float* alds;   // [KP][cap] Gaussian coefficients, k-major (model-buffer path with SLOTS == 0)
 };
 
 __host__ __device__ inline size_t lds_floats(int W, int KP, int M2P) {
   const size_t R = W + 1;
   return 2 * R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 2 * (size_t)W * KP + 2 * (size_t)W * CS + W +
-         2 * R * M2P + kWaves * KP + KP + W + (W + 1);
+         2 * R * M2P + kWaves * KP + KP + W + (W + 1) + 2 * (size_t)W * KP;
 }
 
 // LDS budget of one training workgroup (one per CU; static LDS aside).
@@ -164,6 +166,8 @@ __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
   s.aev = p; p += KP;
   s.omega = p; p += W;
   s.qs = p; p += W + 1;
+  s.vb = p; p += W * KP;
+  s.vd = p; p += W * KP;
   s.alds = p;
   return s;
 }
@@ -317,6 +321,19 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   const int wm = 16 * wave + col;           // component of this lane's weight-tile column
   const int etile = (wave - NWT) & (kWaves - 1);
   floatx4 wacc = {0.0f, 0.0f, 0.0f, 0.0f};
+  // Initial filter: f_0 = 0, or the model's linear part (w = wL v) for a
+  // linear start or a continued training.
+  if (cm.init != kInitZero && wowner) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = 4 * grp + v;
+      wacc[v] = (k < K && wm < M2) ? wout[(k0 + k) * M2 + wm] / cm.wl : 0.0f;
+    }
+  }
+  // A continued training resumes the dictionary ring after the n0 samples
+  // the model has seen; its window starts afresh.
+  const int n0 = cm.init == kInitContinue ? __builtin_amdgcn_readfirstlane(state[2]) : 0;
+  const int size0 = n0 < cap ? n0 : cap;      // entries in use at the start
 
   // Register-resident slots (SLOTS > 0): slot tid + kThreads * u.
   constexpr int DS = SLOTS > 0 && !ROWS ? SLOTS : 1;     // slots whose vectors are held here
@@ -332,17 +349,31 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     if constexpr (!ROWS) {
 #pragma unroll
       for (int u = 0; u < SLOTS; ++u) {
-        dnorm[u] = 0.0f;
+        const int slot = tid + kThreads * u;
+        const bool used = slot < size0;
+        float n4[4] = {0.0f, 0.0f, 0.0f, 0.0f};    // grouped as ||r_n||^2 in phase A
 #pragma unroll
-        for (int m = 0; m < M2P; ++m) dreg[u][m] = 0.0f;
+        for (int m = 0; m < M2P; ++m) {
+          dreg[u][m] = (used && m < M2) ? dict[(size_t)m * cap + slot] : 0.0f;
+          n4[m & 3] = fmaf(dreg[u][m], dreg[u][m], n4[m & 3]);
+        }
+        dnorm[u] = (n4[0] + n4[1]) + (n4[2] + n4[3]);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) areg[u][k] = (used && k < K) ? alpha[(size_t)slot * Kt + k0 + k] : 0.0f;
       }
     }
   } else if constexpr (SLOTS == 0) {
-    // Dictionary in the model buffer, coefficients in LDS; start from an empty one.
-    for (int i = tid; i < cap * KP; i += kThreads) s.alds[i] = 0.0f;
+    // Dictionary in the model buffer, coefficients in LDS (those of a
+    // continued model loaded, else an empty dictionary).
+    for (int i = tid; i < cap * KP; i += kThreads) {
+      const int k = i / cap, slot = i - k * cap;
+      s.alds[i] = (slot < size0 && k < K) ? alpha[(size_t)slot * Kt + k0 + k] : 0.0f;
+    }
   } else {
-    // Dictionary and coefficients in the model buffers; start from an empty one.
-    for (size_t i = tid; i < (size_t)cap * K; i += kThreads) alpha[(i / K) * Kt + k0 + i % K] = 0.0f;
+    // Dictionary and coefficients in the model buffers (a continued model's
+    // are used in place; otherwise start from an empty dictionary).
+    if (cm.init != kInitContinue)
+      for (size_t i = tid; i < (size_t)cap * K; i += kThreads) alpha[(i / K) * Kt + k0 + i % K] = 0.0f;
   }
   if (tid == 0) block_flags = 0;
   int flags = 0;
@@ -384,7 +415,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   }
   __syncthreads();
 
-  int sn = 0, nw = 0, nr = 0;               // n % cap, n % W, n % R
+  int sn = n0 % cap, nw = 0, nr = 0;        // (n0 + n) % cap, n % W, n % R
   // One training step; kr / kwv: the prefetched kernel values of this step
   // (rows training), refilled with those of step n + 2 once used.
   auto step = [&](const int n, float* kr, float& kwv) {
@@ -419,9 +450,10 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       for (int m = 0; m < M2; ++m) n4[m & 3] = fmaf(rrow[m], rrow[m], n4[m & 3]);
       nn = (n4[0] + n4[1]) + (n4[2] + n4[3]);
     }
-    const bool evicting = n >= cap;
-    const int L = n + 1 < W ? n + 1 : W;    // |J_n|
-    const int evlo = n - cap + 1;           // oldest entry in the dictionary after the append
+    const int ng = n0 + n;                  // global index of r_n (dictionary ring)
+    const bool evicting = ng >= cap;
+    const int L = n + 1 < W ? n + 1 : W;    // |J_n| (the window is local)
+    const int evlo = ng - cap + 1;          // oldest entry in the dictionary after the append
     if (tid < KP) s.bwin[nw * KP + tid] = tid < K ? bv : 0.0f;
     if constexpr (ROWS) {
       // Gram entries of r_n against the window members, one lag per thread
@@ -454,12 +486,12 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
           for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
         }
-        if (slot < cap && slot <= n) {
-          const int back = ring_sub(sn, slot, cap);   // this slot holds sample n - back
+        if (slot < cap && slot <= ng) {
+          const int back = ring_sub(sn, slot, cap);   // this slot holds sample ng - back
           const float kg = kr[u];
 #pragma unroll
           for (int k = 0; k < KP; ++k) part[k] = fmaf(areg[u][k], kg, part[k]);
-          const int mv = n - back - evlo;
+          const int mv = ng - back - evlo;
           if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
         }
       }
@@ -481,8 +513,8 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
           for (int k = 0; k < KP; ++k) areg[u][k] = 0.0f;
         }
-        if (slot < cap && slot <= n) {
-          const int back = ring_sub(sn, slot, cap);   // this slot holds sample n - back
+        if (slot < cap && slot <= ng) {
+          const int back = ring_sub(sn, slot, cap);   // this slot holds sample ng - back
           float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
           for (int m = 0; m < M2P; ++m) d4[m & 3] = fmaf(rn[m], dreg[u][m], d4[m & 3]);
@@ -498,7 +530,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
             s.gram[ir * 2 * R + nr] = g;
             s.gram[ir * 2 * R + nr + R] = g;
           }
-          const int mv = n - back - evlo;
+          const int mv = ng - back - evlo;
           if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
         }
       }
@@ -510,7 +542,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       constexpr int SB0 = M2P >= 64 ? 1 : 64 / M2P;
       constexpr int SB = KP == 16 && SB0 > 2 ? 2 : SB0;   // 16 users: bounded by their coefficient registers
       constexpr int MB = M2P >= 64 ? 64 : M2P;
-      const int nslot = (n + 1 < cap ? n + 1 : cap);        // slots in use after the append
+      const int nslot = (ng + 1 < cap ? ng + 1 : cap);      // slots in use after the append
       if (tid == (sn & (kThreads - 1))) {                   // append (and evict)
         if constexpr (SLOTS == 0) {
           if (evicting)
@@ -584,7 +616,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
             s.gram[ir * 2 * R + nr] = g;
             s.gram[ir * 2 * R + nr + R] = g;
           }
-          const int mv = n - back - evlo;
+          const int mv = ng - back - evlo;
           if (mv >= 0 && mv <= W - 2) s.evkr[nw * EVS + mv] = kg;
         }
       }
@@ -605,7 +637,24 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 
     // ------------------------------------------------------------ phase C
     // Every operand is loaded before the first use (one LDS round trip).
+    // Position weights: c = mu q_j beta at once.  Violation weights (q_kj
+    // proportional to member j's distance to its slab, per user): beta and
+    // the distance are parked in LDS and c is formed after a barrier, once
+    // the distances of all members are there.
+    const bool vweights = cm.weights == kWeightsViolation;
     const float qscale = s.qs[L];
+    // c of member p (ring row jw, dictionary slot `slot`) and user k: the
+    // coefficient ring and, on the model-buffer paths, the Gaussian
+    // coefficient (one (member, user) pair per thread; the barrier after
+    // phase C orders it before every later read)
+    auto commit = [&](int p, int k, int jw, int slot, float c, float aold) {
+      if (k < K) {
+        if constexpr (SLOTS == 0) s.alds[k * cap + slot] = fmaf(c, cm.wg, aold);
+        if constexpr (SLOTS < 0) alpha[(size_t)slot * Kt + k0 + k] = fmaf(c, cm.wg, aold);
+      }
+      s.c[jw * CS + k] = c;
+      s.c[(jw + W) * CS + k] = c;
+    };
     for (int t = tid; t < L * KP; t += kThreads) {
       const int p = t / KP, k = t - p * KP;
       const int jw = ring_sub(nw, p, W);
@@ -632,18 +681,31 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       const float e = p == 0 ? esum : eupd;
       const float x = e - bw;
       const float beta = -soft_threshold(x, cm.eps) * ik;
-      const float c = k < K ? qscale * om * beta : 0.0f;
       if (k < K) {
         s.e[jw * KP + k] = e;
         if (!isfinite(x)) flags |= 1;
-        // Gaussian coefficient of member n - p (model-buffer paths), one
-        // (member, user) pair per thread; the barrier below orders it
-        // before every later read.
-        if constexpr (SLOTS == 0) s.alds[k * cap + slot] = fmaf(c, cm.wg, aold);
-        if constexpr (SLOTS < 0) alpha[(size_t)slot * Kt + k0 + k] = fmaf(c, cm.wg, aold);
       }
-      s.c[jw * CS + k] = c;
-      s.c[(jw + W) * CS + k] = c;
+      if (vweights) {
+        s.vb[p * KP + k] = beta;
+        s.vd[p * KP + k] = k < K ? fmaxf(fabsf(x) - cm.eps, 0.0f) : 0.0f;
+      } else {
+        commit(p, k, jw, slot, k < K ? qscale * om * beta : 0.0f, aold);
+      }
+    }
+    if (vweights) {
+      __syncthreads();
+      for (int t = tid; t < L * KP; t += kThreads) {
+        const int p = t / KP, k = t - p * KP;
+        const int jw = ring_sub(nw, p, W);
+        const int slot = ring_sub(sn, p, cap);
+        float tot = 0.0f;
+        for (int i = 0; i < L; ++i) tot += s.vd[i * KP + k];
+        float aold = 0.0f;
+        if constexpr (SLOTS == 0) aold = s.alds[k * cap + slot];
+        if constexpr (SLOTS < 0) aold = alpha[(size_t)slot * Kt + k0 + (k < K ? k : 0)];
+        const float c = (k < K && tot > 0.0f) ? cm.mu * (s.vd[p * KP + k] / tot) * s.vb[p * KP + k] : 0.0f;
+        commit(p, k, jw, slot, c, aold);
+      }
     }
     if (tid < M2P && n + 1 < T) {           // r_{n+1} into its ring row (no member of J_n)
       const int nr1 = nr + 1 == R ? 0 : nr + 1;
@@ -682,7 +744,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
 #pragma unroll
       for (int u = 0; u < SLOTS; ++u) {
         const int slot = tid + kThreads * u;
-        if (slot < cap && slot <= n) {
+        if (slot < cap && slot <= ng) {
           const int back = ring_sub(sn, slot, cap);
           if (back < L) {
             const float* cj = cbase - back * CS;
@@ -738,8 +800,8 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       }
     }
   } else {
-    // Slots never written (T < cap) are cleared so detection may sum them.
-    for (int slot = T + tid; slot < cap; slot += kThreads)
+    // Slots never written (n0 + T < cap) are cleared so detection may sum them.
+    for (int slot = n0 + T + tid; slot < cap; slot += kThreads)
       for (int m = 0; m < M2; ++m) dict[(size_t)m * cap + slot] = 0.0f;
     if constexpr (SLOTS == 0)
       for (int i = tid; i < cap * K; i += kThreads) {
@@ -758,9 +820,10 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   __syncthreads();
   if (tid == 0) {
     if (lead) {
-      state[0] = T < cap ? T : cap;
-      state[1] = T % cap;
-      state[2] = T;
+      const int Tg = n0 + T;                // samples seen in all
+      state[0] = Tg < cap ? Tg : cap;
+      state[1] = Tg % cap;
+      state[2] = Tg;
     }
     // A detector trained as one job overwrites its flags word; the groups of
     // a split detector OR theirs into it (cleared by the kernel-rows launch).

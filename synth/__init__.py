@@ -266,3 +266,36 @@ def make_instance_device(spec: InstanceSpec, device) -> DeviceInstance:
     sym_p = np.stack([b_p.real, b_p.imag], axis=-1).astype(np.float32)
     return DeviceInstance(spec=spec, rx_pilot=_to_planar(r_p), sym_pilot=sym_p, rx_data=rx, truth=truth,
                           scale=float(scale), extras={"H": H, "p": p})
+
+
+def make_drifting_blocks(spec: InstanceSpec, blocks: int, step_rad: float):
+    """Pilots on channel H and then `blocks` data blocks of spec.S symbols
+    each on a slowly changing channel H_b = cos(b a) H + sin(b a) H2 (a =
+    step_rad; H2 an independent draw, so every H_b has the statistics of H).
+    Unit powers, no PA model; the pilot block's scale applies throughout.
+    Returns (pilot Instance with the block-0 data, list of (rx [S][2M]
+    float32, truth [S][K] uint8, sym [S][K][2] float32) per block)."""
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    K, M = spec.K, spec.M
+    H = (rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))) / np.sqrt(2.0)
+    H2 = (rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))) / np.sqrt(2.0)
+    n0 = 10.0 ** (-spec.snr_db / 10.0)
+
+    def block(n, Hb):
+        b, idx = _draw_symbols(rng, n, K, spec.modulation)
+        noise = (rng.standard_normal((n, M)) + 1j * rng.standard_normal((n, M))) * np.sqrt(n0 / 2.0)
+        return b @ Hb.T + noise, b, idx
+
+    r_p, b_p, _ = block(spec.P, H)
+    scale = 1.0 / np.sqrt(np.mean(np.sum(np.abs(r_p) ** 2, axis=1)))
+    out = []
+    for bi in range(blocks):
+        Hb = np.cos(bi * step_rad) * H + np.sin(bi * step_rad) * H2
+        r, b, idx = block(spec.S, Hb)
+        out.append((_to_planar(r * scale), label_of(idx[..., 0], idx[..., 1], spec.modulation),
+                    np.stack([b.real, b.imag], axis=-1).astype(np.float32)))
+    pil = Instance(spec=spec, rx_pilot=_to_planar(r_p * scale),
+                   sym_pilot=np.stack([b_p.real, b_p.imag], axis=-1).astype(np.float32),
+                   rx_data=out[0][0], sym_data=out[0][2], truth=out[0][1], scale=float(scale),
+                   extras={"H": H, "H2": H2, "n0": n0})
+    return pil, out

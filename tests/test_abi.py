@@ -61,7 +61,7 @@ def _model(M2=32, K=6, cap=256, ptr=1, packed=1):
 
 def _params(**kw):
     base = dict(sigma2=0.5, eps=0.05, mu=1.0, w_lin=0.5, w_gauss=0.5, window=16, dict_cap=256,
-                reserved=0, pos_weights=None)
+                init=0, pos_weights=None, weights=0, reserved=0)
     base.update(kw)
     return A._CParams(**base)
 
@@ -71,6 +71,8 @@ BAD_TRAIN = [
     (dict(mu=0.0), 1), (dict(mu=2.0), 1), (dict(w_lin=0.0, w_gauss=0.0), 1),
     (dict(w_lin=-1.0), 1), (dict(window=0), 1), (dict(window=65, dict_cap=256), 3),
     (dict(dict_cap=8, window=16), 1), (dict(reserved=1), 1),
+    (dict(init=3), 1), (dict(init=-1), 1), (dict(init=1, w_lin=0.0, w_gauss=1.0), 1),
+    (dict(init=2, w_lin=0.0, w_gauss=1.0), 1), (dict(weights=2), 1),
 ]
 
 
@@ -358,3 +360,42 @@ def test_tune_cache_save_and_load(tmp_path):
     A.shutdown()                                            # releases the cache
     A.tune_save(str(out))
     assert json.loads(out.read_text()) == {}
+
+
+@needs_lib
+def test_weights_modes_and_init_validation():
+    """Violation weights exclude position weights; batches and the
+    allocation-free entry point do not continue models (their kernel rows
+    cover the pilots only)."""
+    L = A.library()
+    w = (ctypes.c_float * 16)(*([1.0] * 16))
+    pw = ctypes.cast(w, ctypes.POINTER(ctypes.c_float))
+    m = _model()
+    assert L.apsm_train(ctypes.byref(_params(weights=1, pos_weights=pw)), 32, 6, 64, 1, 1, ctypes.byref(m),
+                        None) == A.ERR_INVALID_ARG
+    items = (A._CBatchItem * 1)(_item())
+    h = ctypes.c_void_p()
+    assert L.apsm_batch_create(ctypes.byref(_params(init=2)), items, 1, ctypes.byref(h)) == 3
+    assert L.apsm_train_noalloc(ctypes.byref(_params(init=2)), 32, 6, 64, 1, 1, ctypes.byref(m), None) == 3
+    assert L.apsm_batch_create(ctypes.byref(_params(init=1, weights=1)), items, 1, ctypes.byref(h)) == 0
+    L.apsm_batch_destroy(h)
+
+
+@needs_lib
+def test_mmse_and_track_validation():
+    L = A.library()
+    assert L.apsm_linear_mmse(None, 0.1, 32, 6, 1, 1, None) == 1
+    assert L.apsm_linear_mmse(1, -0.1, 32, 6, 1, 1, None) == 1
+    assert L.apsm_linear_mmse(1, float("nan"), 32, 6, 1, 1, None) == 1
+    assert L.apsm_linear_mmse(1, 0.1, 31, 6, 1, 1, None) == 2
+    assert L.apsm_linear_mmse(1, 0.1, 256, 6, 1, 1, None) == 3
+    assert L.apsm_linear_mmse(1, 0.1, 32, 17, 1, 1, None) == 3
+    assert L.apsm_linear_mmse(1, 0.1, 32, 6, 0, 1, None) == 0          # nothing to do
+    p, m = _params(), _model()
+    assert L.apsm_track(ctypes.byref(p), ctypes.byref(m), 10, 1, 0, 1, None, None, None, None) == 1   # no modulation
+    assert L.apsm_track(ctypes.byref(p), ctypes.byref(m), 10, 1, 2, None, None, None, None, None) == 1
+    assert L.apsm_track(ctypes.byref(p), ctypes.byref(m), -1, 1, 2, 1, None, None, None, None) == 2
+    assert L.apsm_track(ctypes.byref(p), ctypes.byref(m), 0, None, 2, None, None, None, None, None) == 0
+    assert L.apsm_track(ctypes.byref(_params(dict_cap=300)), ctypes.byref(m), 10, 1, 2, 1, None, None, None,
+                        None) == 2
+    assert L.apsm_track(ctypes.byref(p), ctypes.byref(m), 10, 1, 2, 1, None, 1, None, None) == 1   # truth w/o count
