@@ -3,6 +3,8 @@ ABI): detectors of different shapes in one training launch and one detection
 launch, against the FP64 oracle and against the one-detector-per-launch path
 (apsm_train / apsm_detect) on the same inputs.  Rules and tolerances:
 tests/parity_util.py."""
+import os
+
 import numpy as np
 import pytest
 
@@ -270,6 +272,23 @@ def test_batch_full_mixed_workload_sampled():
         outside, inside = compare_hard(it.hard.cpu().numpy()[idx], soft_ref, spec.modulation)
         assert outside == 0, (i, outside, inside)
         print(f"[result] detector {i} (K={spec.K}, M={spec.M}, D={D}): worst {worst:.2e}", flush=True)
+    # the hardest detectors (largest dictionary; largest among 8 users, 16-QAM,
+    # 2M = 64) against the oracle results stored by
+    # tests/golden/make_oracle_samples.py
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "mixed_large.npz"))
+    for i in [int(v) for v in g["which"]]:
+        spec, D = specs[i]
+        inst, it = insts[i], items[i]
+        w_ref, a_ref = g[f"w_{i}"], g[f"alpha_{i}"]
+        assert np.abs(it.model.w.cpu().numpy() - w_ref).max() <= REL_TOL * np.abs(w_ref).max(), i
+        assert np.abs(it.model.alpha.cpu().numpy() - a_ref).max() <= REL_TOL * np.abs(a_ref).max(), i
+        idx, soft_ref = g[f"idx_{i}"], g[f"soft_{i}"]
+        worst, _ = compare_soft(it.soft.cpu().numpy()[idx], soft_ref, spec.modulation)
+        assert worst <= REL_TOL, (i, worst)
+        outside, inside = compare_hard(it.hard.cpu().numpy()[idx], soft_ref, spec.modulation)
+        assert outside == 0, (i, outside, inside)
+        print(f"[result] stored detector {i} (K={spec.K}, M={spec.M}, D={D}, {spec.modulation}): "
+              f"worst {worst:.2e}, band mismatches {inside}", flush=True)
 
 
 def test_both_detection_kernels_on_dual_shapes(tmp_path):

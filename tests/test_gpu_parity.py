@@ -156,43 +156,6 @@ def test_end_to_end_parity(name):
           f"SER gpu {errs.sum() / hard.size:.4g}", flush=True)
 
 
-# --------------------------------------------------- full-size slot, sampled
-
-def test_full_slot_sampled_parity():
-    """Realistic slot (K=6, 16 antennas, near-far, Rapp PA, 1024 pilots,
-    1,048,576 data symbols, W=32, cap 1024) at 5 dB, in the launch
-    configuration the benchmark times; the oracle evaluates a sample of the
-    outputs one by one."""
-    announce("full slot 5 dB, S=1048576")
-    spec = synth.spec_slot(5.0)
-    inst = synth.make_instance(spec)
-    p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, dict_cap=1024)
-    m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
-    out = A.detect(m, cuda(inst.rx_data), modulation="qpsk", truth=cuda(inst.truth))
-    torch.cuda.synchronize()
-    f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, oracle_params(p))
-    assert np.abs(m.w.cpu().numpy() - f.w).max() <= REL_TOL * np.abs(f.w).max()
-    rng = np.random.default_rng(7)
-    S = spec.S
-    idx = np.unique(np.concatenate([np.arange(256), np.arange(S - 256, S),
-                                    rng.integers(0, S, 1536)]))
-    soft_ref = O.detect_planar(f, inst.rx_data[idx])
-    soft = out["soft"].cpu().numpy()[idx]
-    worst, _ = compare_soft(soft, soft_ref, "qpsk")
-    assert worst <= REL_TOL, worst
-    hard = out["hard"].cpu().numpy()
-    outside, inside = compare_hard(hard[idx], soft_ref, "qpsk")
-    assert outside == 0, (outside, inside)
-    errs = out["errors"].cpu().numpy()
-    np.testing.assert_array_equal(errs, O.symbol_errors(hard, inst.truth))
-    # SER on the sampled symbols is identical when no decision fell in the band
-    if inside == 0:
-        ref_lab = O.decide(soft_ref, "qpsk")
-        np.testing.assert_array_equal(O.symbol_errors(ref_lab, inst.truth[idx]),
-                                      O.symbol_errors(hard[idx], inst.truth[idx]))
-    print(f"[result] full slot: worst {worst:.2e}, SER {errs.sum() / hard.size:.4g}", flush=True)
-
-
 # ----------------------------------------------------------------- behaviour
 
 def test_errors_accumulate_and_outputs_optional():

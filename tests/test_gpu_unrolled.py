@@ -2,7 +2,8 @@
 the C ABI and the autograd binding): the loss against the FP64 reference
 forward, the hand-written adjoint against the FP64 reference gradient
 (automatic differentiation, itself pinned to finite differences) and against
-central finite differences of the FP64 forward, to 1e-3 relative; checkpoint
+central finite differences of the FP64 forward, to 1e-3 relative per
+component (components below 1e-3 of the largest judged on that floor); checkpoint
 interval invariance and repeatability."""
 import numpy as np
 import pytest
@@ -15,6 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 GRAD_TOL = 1e-3
+GRAD_FLOOR = 1e-3
 
 
 def announce(msg):
@@ -37,12 +39,17 @@ def gpu_loss_grad(theta, dev, passes, ckpt, wl=0.5, wg=0.5):
     return float(L.detach()), th.grad.detach().cpu().numpy().astype(np.float64)
 
 
-def assert_grad_close(g, ref, tol=GRAD_TOL):
-    scale = np.abs(ref).max()
-    assert np.abs(g - ref).max() <= tol * scale, (g, ref)
-    big = np.abs(ref) > 0.05 * scale
-    rel = np.abs(g - ref)[big] / np.abs(ref)[big]
-    assert rel.max() <= 10 * tol, (g, ref)
+def assert_grad_close(g, ref, tol=GRAD_TOL, floor=GRAD_FLOOR):
+    """Every component to `tol` relative: |g_i - ref_i| <= tol * max(|ref_i|,
+    floor * max_j |ref_j|).  The floor covers components that nearly cancel
+    (far below the largest), whose FP32 rounding is set by the size of the
+    terms summed into them rather than by their own value."""
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.maximum(np.abs(ref), floor * np.abs(ref).max())
+    rel = np.abs(np.asarray(g, dtype=np.float64) - ref) / scale
+    print(f"[result] gradient: worst per-component error {rel.max():.2e} at component {int(rel.argmax())} "
+          f"(|ref| {abs(ref[rel.argmax()]):.3e}, largest {np.abs(ref).max():.3e})", flush=True)
+    assert rel.max() <= tol, (g, ref, rel)
 
 
 CASES = {
