@@ -6,8 +6,8 @@ A_sat = 1, 20 dB) received on 64 antennas (2M = 128), 8192 pilot symbols
 (16,384 real training steps, window 32, dictionary capacity 8192) and
 4,194,304 data symbols.  One step trains the 16 detectors (kernel rows in one
 launch, training in one launch, packing) and detects all 16 x 4,194,304
-received vectors with decisions and symbol-error counts (one persistent
-launch).  Steps are pipelined over two model sets on two streams (the
+received vectors with decisions and symbol-error counts (one launch, a
+workgroup per 128 received vectors).  Steps are pipelined over two model sets on two streams (the
 training of step k runs beside the detection of step k - 1); every step still
 trains 16 detectors and detects 16 frames.  Inputs are synthetic (seeded),
 generated on the device, and resident in HBM before the timed region.
@@ -36,6 +36,36 @@ METRIC = ("detected symbols/s and kernel evals/s vs roofline at oracle SER; "
 PEAK_FP16_MFMA_TFLOPS = 256 * 4096 * 2.4e9 / 1e12               # 2516.6
 # FP32 vector peak: 256 CUs x 4 SIMDs x 32 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_FP32_VALU_TFLOPS = 256 * 4 * 32 * 2 * 2.4e9 / 1e12         # 157.3
+
+
+def detection_roofline(kernel, det_s, vectors, D, M2, K, M2P):
+    """Roofline of one two-contraction detection launch over `vectors` real
+    vectors against D dictionary entries each.  `achieved` counts the
+    method's algorithmic flops, D (2 2M + 3 + 2K) + 2 2M (K + 1) per real
+    vector (distance block, norm combine, coefficients, linear part), over
+    the FP16 matrix-core peak, the type the contractions execute in.  The
+    split-FP16 formulation executes three FP16 products per FP32 product, on
+    operands padded to 2M -> M2P and K -> 16: those executed flops, their
+    fraction of the same peak, the algorithmic rate as a multiple of the FP32
+    peak (the bound of any FP32 formulation) and the VALU flop-equivalents
+    per evaluation (exponent FMA 2, exp2 8, hi/lo split 6) are reported
+    beside it."""
+    evals = vectors * D
+    alg = vectors * (D * (2 * M2 + 3 + 2 * K) + 2 * M2 * (K + 1))
+    executed = evals * 6 * (M2P + 16) + vectors * 6 * M2P * 16
+    achieved = alg / det_s / 1e12
+    return {
+        "kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_MFMA_TFLOPS,
+        "unit": "TFLOP/s", "frac": achieved / PEAK_FP16_MFMA_TFLOPS,
+        "per_launch": {
+            "real_vectors": vectors, "kernel_evals": evals, "algorithmic_flops": alg,
+            "algorithmic_flops_per_real_vector": alg / vectors, "avg_ms": det_s * 1e3,
+            "executed_fp16_mfma_flops": executed,
+            "executed_fp16_mfma_frac": executed / det_s / 1e12 / PEAK_FP16_MFMA_TFLOPS,
+            "algorithmic_rate_over_fp32_peak": achieved / PEAK_FP32_VALU_TFLOPS,
+            "valu_frac_of_fp32_peak": evals * 16 / det_s / 1e12 / PEAK_FP32_VALU_TFLOPS,
+        },
+    }
 
 # HBM bytes per launch of the batched two-contraction detection kernel on the
 # headline workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
@@ -219,17 +249,10 @@ def run_large(args, dev, s_train, s_det):
 
     det_ms = [a.elapsed_time(b) for a, b in det_events]
     det_s = float(np.mean(det_ms)) / 1e3
-    M2P = 128
     evals = n * 2 * S * cap                                     # (real vector, entry) pairs per launch
-    # FP16 matrix-core flops: three split products of the distance block
-    # (2 x 2M) and of the coefficient block (2 x 16 users) per evaluation,
-    # and of the linear part (2 x 2M x 16) per real vector
-    mfma_flops = evals * 6 * (M2P + 16) + n * 2 * S * 6 * M2P * 16
-    achieved = mfma_flops / det_s / 1e12
-    # the algorithmic FP32 count of the method: D (2 2M + 3 + 2K) + 2 2M (K + 1) per real vector
-    alg_flops = n * 2 * S * (cap * (2 * M2 + 3 + 2 * K) + 2 * M2 * (K + 1))
-    # VALU per evaluation: exponent FMA (2), exp2 (four issue slots, 8), hi/lo split (3 ops, 6)
-    valu_flops = evals * 16
+    roof = detection_roofline("detect_wide_batch_kernel<128>", det_s, n * 2 * S, cap, M2, K, 128)
+    roof["traffic"] = measured_traffic()
+    roof["per_launch"]["launches_timed"] = len(det_ms)
 
     out = {
         "value": n * S * K / (elapsed / args.steps),
@@ -240,18 +263,7 @@ def run_large(args, dev, s_train, s_det):
                          "eps=0.05, mu=1, dictionary cap 8192); one step trains and detects all 16"),
             "instances_per_step": n, "data_symbols": S, "pilots": P, "users": K, "antennas": M2 // 2,
         },
-        "roofline": {
-            "kernel": "detect_wide_batch_kernel<128>", "bound": "mfma", "achieved": achieved,
-            "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP16_MFMA_TFLOPS,
-            "traffic": measured_traffic(),
-            "per_launch": {"kernel_evals": evals, "fp16_mfma_flops": mfma_flops,
-                           "fp16_mfma_flops_per_eval": 6 * (M2P + 16), "avg_ms": det_s * 1e3,
-                           "launches_timed": len(det_ms),
-                           "method_fp32_flops": alg_flops,
-                           "method_fp32_tflops_equivalent": alg_flops / det_s / 1e12,
-                           "valu_flop_equivalents": valu_flops,
-                           "valu_frac_of_fp32_peak": valu_flops / det_s / 1e12 / PEAK_FP32_VALU_TFLOPS},
-        },
+        "roofline": roof,
         "detect_only": {"user_symbols_per_s": n * S * K / det_s, "kernel_evals_per_s": evals / det_s,
                         "ms_one_launch_16_instances": det_s * 1e3},
         "train_ms_16_instances": {"kernel_rows": rows_ms, "training_and_packing": train_ms},
@@ -479,8 +491,6 @@ def run_slot(args, dev, s_train, s_det):
     det_s = float(np.mean([a.elapsed_time(b) for a, b in det_events])) / 1e3
     n = len(insts)
     evals = n * 2 * S * params.dict_cap
-    mfma_flops = evals * 6 * (32 + 16) + n * 2 * S * 6 * 32 * 16
-    achieved = mfma_flops / det_s / 1e12
     ser = {f"{s:g}dB": float(e.sum().item()) / (S * K) for s, e in zip(snrs, errs)}
     out = {
         "workload": ("realistic slot: K=6 users QPSK, 16 Rx antennas (2M=32), near-far [-6,0] dB, Rapp PA p=2 "
@@ -492,9 +502,8 @@ def run_slot(args, dev, s_train, s_det):
         "train_ms_4_instances": train_ms,
         "detect_ms_one_launch_4_instances": det_s * 1e3,
         "kernel_evals_per_s": evals / det_s,
-        "roofline": {"kernel": "detect_wide_batch_kernel<32>", "bound": "mfma", "achieved": achieved,
-                     "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP16_MFMA_TFLOPS,
-                     "valu_frac_of_fp32_peak": evals * 16 / det_s / 1e12 / PEAK_FP32_VALU_TFLOPS},
+        "roofline": detection_roofline("detect_wide_batch_kernel<32>", det_s, n * 2 * S, params.dict_cap,
+                                       M2, K, 32),
         "ser_gpu": ser,
     }
     if not args.no_cpu_baseline:

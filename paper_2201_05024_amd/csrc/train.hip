@@ -31,8 +31,10 @@
 // eqn:apsm requires.
 //
 // Dictionary slots are owned round-robin by the threads (slot s by thread
-// s % 256).  When cap * M2 fits, each thread keeps its slots' vectors and
-// coefficients in registers; otherwise they live in the model buffers.
+// s % 512).  When cap * M2 fits, each thread keeps its slots' vectors and
+// coefficients in registers; otherwise the coefficients live in LDS or, with
+// the vectors, in the model buffers.  Training from precomputed kernel rows
+// (the batch path) replaces the row evaluation of phase A by one row read.
 #include "apsm_internal.h"
 
 namespace apsm {
