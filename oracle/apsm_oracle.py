@@ -221,6 +221,39 @@ def beta(e: float, b: float, eps: float, kjj: float) -> float:
     return 0.0
 
 
+# Kinds of the set a training sample defines in H through the value f(r_j)
+# (the generic engine: Sec. I and Sec. VI, the same machinery for other
+# projection-based methods).  Each is {f : f(r_j) in [lo, hi]}, a closed
+# convex set; the hyperslab of eqn:convex_set is the default.
+SET_SLAB = 0        # |f(r) - b| <= eps
+SET_PLANE = 1       # f(r) = b (a hyperplane; eps is not used)
+SET_UPPER = 2       # f(r) <= b + eps (a halfspace)
+SET_LOWER = 3       # f(r) >= b - eps (a halfspace)
+
+
+def set_interval(kind: int, b: float, eps: float):
+    """[lo, hi] of the values f(r_j) the set of this kind admits."""
+    if kind == SET_SLAB:
+        return b - eps, b + eps
+    if kind == SET_PLANE:
+        return b, b
+    if kind == SET_UPPER:
+        return -math.inf, b + eps
+    if kind == SET_LOWER:
+        return b - eps, math.inf
+    raise ValueError(kind)
+
+
+def beta_set(e: float, b: float, eps: float, kjj: float, kind: int) -> float:
+    """Projection onto {f : f(r_j) in [lo, hi]}: P(f) = f + beta kappa(r_j, .)
+    moves f(r_j) to the nearest point of [lo, hi], so beta = (clip(e) - e) /
+    kappa(r_j, r_j) (0 when f(r_j) is already inside)."""
+    if kjj == 0.0:
+        return 0.0
+    lo, hi = set_interval(kind, b, eps)
+    return (min(max(e, lo), hi) - e) / kjj
+
+
 def window(n: int, W: int) -> range:
     """J_n = {n-W+1, .., n} if n >= W-1, else {0, .., n}."""
     return range(n - W + 1, n + 1) if n >= W - 1 else range(0, n + 1)
@@ -241,12 +274,15 @@ class Trainer:
     n0: global index of the first sample of R when continuing a filter that
     has already seen n0 samples: the samples enter its dictionary as
     n0, n0 + 1, .. (FIFO eviction continues across the boundary), while the
-    window J_n starts afresh inside R."""
+    window J_n starts afresh inside R.
+    types: optional [T][K] set kinds (SET_*) per sample and user; None gives
+    the hyperslabs of eqn:convex_set with the three cases of eqn:beta."""
 
     def __init__(self, R: np.ndarray, B: np.ndarray, p: APSMParams,
-                 f0: Optional[Filter] = None, n0: int = 0):
+                 f0: Optional[Filter] = None, n0: int = 0, types: Optional[np.ndarray] = None):
         self.R = np.asarray(R, dtype=np.float64)
         self.B = np.asarray(B, dtype=np.float64)
+        self.types = None if types is None else np.asarray(types, dtype=np.int64)
         self.p = p
         if p.dict_cap is not None and p.dict_cap < p.window:
             raise ValueError("dictionary cap must be at least the window size")
@@ -277,11 +313,21 @@ class Trainer:
         bet = {}
         for j in J:
             kjj = kappa_sum(self.R[j], self.R[j], p.sigma2, p.w_lin, p.w_gauss)
-            bet[j] = np.array([beta(e[j][k], self.B[j, k], p.eps, kjj) for k in range(f.K)])
+            if self.types is None:
+                bet[j] = np.array([beta(e[j][k], self.B[j, k], p.eps, kjj) for k in range(f.K)])
+            else:
+                bet[j] = np.array([beta_set(e[j][k], self.B[j, k], p.eps, kjj, self.types[j, k])
+                                   for k in range(f.K)])
         if p.weight_mode == "violation":
-            # q_kj proportional to the distance of f_n(r_j) to slab C_kj (the
+            # q_kj proportional to the distance of f_n(r_j) to set C_kj (the
             # paper leaves the weights free to prioritise sets adaptively)
-            dist = {j: np.maximum(np.abs(e[j] - self.B[j]) - p.eps, 0.0) for j in J}
+            if self.types is None:
+                dist = {j: np.maximum(np.abs(e[j] - self.B[j]) - p.eps, 0.0) for j in J}
+            else:
+                dist = {}
+                for j in J:
+                    iv = [set_interval(self.types[j, k], self.B[j, k], p.eps) for k in range(f.K)]
+                    dist[j] = np.array([abs(min(max(e[j][k], lo), hi) - e[j][k]) for k, (lo, hi) in enumerate(iv)])
             tot = sum(dist.values())
             qk = {j: np.divide(dist[j], tot, out=np.zeros(f.K), where=tot > 0) for j in J}
         else:
@@ -305,15 +351,28 @@ def train(R: np.ndarray, B: np.ndarray, p: APSMParams,
     return tr.f
 
 
+def sample_types(set_types_pairs: np.ndarray) -> np.ndarray:
+    """[P][K][2] set kinds (real part, imaginary part of each pilot symbol) ->
+    [T][K] in the order of the training sequence (n = 2t + l - 1)."""
+    st = np.asarray(set_types_pairs)
+    P, K, _ = st.shape
+    out = np.empty((2 * P, K), dtype=np.int64)
+    out[0::2] = st[..., 0]
+    out[1::2] = st[..., 1]
+    return out
+
+
 def train_from_pilots(rx_pilot_planar: np.ndarray, sym_pilot_pairs: np.ndarray,
-                      p: APSMParams, f0: Optional[Filter] = None, n0: int = 0) -> Filter:
+                      p: APSMParams, f0: Optional[Filter] = None, n0: int = 0,
+                      set_types: Optional[np.ndarray] = None) -> Filter:
     """Planar float arrays as stored for the library -> Filter: training from
-    f0 (default f_0 = 0) whose dictionary has seen n0 samples before."""
+    f0 (default f_0 = 0) whose dictionary has seen n0 samples before;
+    set_types [P][K][2] (SET_*) or None for hyperslabs."""
     rx = _planar_to_complex(rx_pilot_planar)
     sym = np.asarray(sym_pilot_pairs, dtype=np.float64)
     sym = sym[..., 0] + 1j * sym[..., 1]
     R, B = training_sequence(rx, sym)
-    tr = Trainer(R, B, p, f0=f0, n0=n0)
+    tr = Trainer(R, B, p, f0=f0, n0=n0, types=None if set_types is None else sample_types(set_types))
     for _ in range(len(R)):
         tr.step()
     return tr.f
