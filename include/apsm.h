@@ -89,6 +89,16 @@ extern "C" {
                                       max(|f_n(r_j) - b_kj| - eps, 0) to its slab (0 for all when
                                       none is violated); pos_weights must be NULL               */
 
+/* Kind of the closed convex set a training sample defines through the value
+ * f(r_j) (apsm_params_t.set_types).  The hyperslab is the detector's set
+ * (eqn:convex_set); the others make the training a generic projection engine
+ * (Sec. I and Sec. VI: the GPU design serves other projection-based methods
+ * in RKHSs).  Each projection moves f(r_j) to the nearest admitted value. */
+#define APSM_SET_SLAB    0         /* |f(r_j) - b_j| <= eps                          */
+#define APSM_SET_PLANE   1         /* f(r_j) = b_j (eps not used)                    */
+#define APSM_SET_UPPER   2         /* f(r_j) <= b_j + eps                            */
+#define APSM_SET_LOWER   3         /* f(r_j) >= b_j - eps                            */
+
 /* Design parameters of the iteration (HOST struct).
  *  sigma2      Gaussian kernel width sigma^2 > 0 (Sec. II-A).
  *  eps         hyperslab half-width eps >= 0 (eqn:convex_set).
@@ -109,7 +119,13 @@ extern "C" {
  *              newest set j = n), q_j = omega[n-j] / sum_{i in J_n} omega[n-i];
  *              NULL for uniform q_j = 1/|J_n| (eqn:apsm's weights, Sec. II-D).
  *  weights     APSM_WEIGHTS_*: position weights, or weights proportional to the
- *              slab violation (Sec. II-D: the q_j may prioritise sets adaptively). */
+ *              slab violation (Sec. II-D: the q_j may prioritise sets adaptively).
+ *  set_types   DEVICE pointer to uint8 APSM_SET_* kinds laid out as the pilot
+ *              symbols, [P][K][2] (real, imaginary part; [n_inst][P][K][2] for
+ *              apsm_train_batched), or NULL for hyperslabs everywhere.  With
+ *              violation weights the distance is the one to the sample's set.
+ *              Taken by apsm_train, apsm_train_batched and apsm_pocs; the
+ *              other entry points return APSM_ERR_UNSUPPORTED for non-NULL. */
 typedef struct apsm_params {
   float sigma2;
   float eps;
@@ -122,6 +138,7 @@ typedef struct apsm_params {
   const float* pos_weights;
   int32_t weights;
   int32_t reserved;           /* must be 0 */
+  const uint8_t* set_types;
 } apsm_params_t;
 
 /* A trained detector: the whole filter state (Sec. III-B: dictionary plus
@@ -243,6 +260,46 @@ int apsm_linear_mmse(const float* h, float n0, int M2, int K, int n_inst, float*
  * Asynchronous on `stream`. */
 int apsm_track(const apsm_params_t* params, const apsm_model_t* model, int S, const float* rx, int modulation,
                float* decided, uint8_t* hard, const uint8_t* truth, int64_t* err_count, void* stream);
+
+/* ---- generic projection engine: ball projection and cyclic POCS ------
+ * The ball B = {f : ||f_k||_H <= radius} around f = 0 in the sum space H
+ * with the norm of Fact 1 (Sec. II-B),
+ *     ||f_k||^2 = ||w_k||^2 / w_lin + alpha_k^T G alpha_k / w_gauss,
+ * G the Gaussian Gram matrix of the dictionary entries in use (a zero
+ * weight leaves its part out).  The projection onto B scales user k's
+ * w_k and alpha_k by radius / ||f_k|| when ||f_k|| > radius, else leaves
+ * them unchanged.  The Gaussian part of the norm is evaluated by the
+ * detection kernels on the model's own dictionary vectors. */
+
+/* Workspace bytes for apsm_project_ball and apsm_pocs with this model shape
+ * (pure host function; 0 for shapes beyond this build's limits). */
+size_t apsm_ball_workspace_bytes(int M2, int K, int dict_cap);
+
+/* Projection of every user's filter onto the ball, then repacking.
+ *  model      a trained model (its packed form current).
+ *  sigma2, w_lin, w_gauss
+ *             the kernel width and sum-space weights the model was trained
+ *             with (> 0, >= 0, >= 0, weights not both 0).
+ *  radius     >= 0, finite.
+ *  workspace  DEVICE, 256-byte aligned, >= apsm_ball_workspace_bytes bytes.
+ *  norms      [K] DEVICE output or NULL: ||f_k||_H before the projection.
+ * Asynchronous on `stream`. */
+int apsm_project_ball(const apsm_model_t* model, float sigma2, float w_lin, float w_gauss, float radius,
+                      void* workspace, size_t ws_bytes, float* norms, void* stream);
+
+/* Cyclic projections (POCS) of one detector: `cycles` times, the windowed
+ * parallel projections over the P pilots' sets (as apsm_train: from
+ * params->init in the first cycle, continued in the later ones, the
+ * samples re-entering the dictionary ring with new indices and the window
+ * starting afresh), then the projection onto the ball of `radius`.
+ *  params     HOST, as for apsm_train (set_types allowed); cycles > 1 needs
+ *             w_lin > 0.
+ *  cycles     >= 1.
+ *  workspace  as for apsm_project_ball.
+ * Asynchronous on `stream`. */
+int apsm_pocs(const apsm_params_t* params, int M2, int K, int P, const float* rx_pilot, const float* sym_pilot,
+              const apsm_model_t* model, float radius, int cycles, void* workspace, size_t ws_bytes,
+              void* stream);
 
 /* ---- batches of detectors with different shapes ----------------------
  * Many independent detectors (each its own user count K, input dimension

@@ -39,11 +39,15 @@ class _CParams(ctypes.Structure):
                 ("w_lin", ctypes.c_float), ("w_gauss", ctypes.c_float),
                 ("window", ctypes.c_int32), ("dict_cap", ctypes.c_int32),
                 ("init", ctypes.c_int32), ("pos_weights", ctypes.POINTER(ctypes.c_float)),
-                ("weights", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("weights", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("set_types", ctypes.c_void_p)]
 
 
 INIT = {"zero": 0, "linear": 1, "continue": 2}
 WEIGHTS = {"position": 0, "violation": 1}
+# Set kinds of the training samples (APSM_SET_*), as uint8 codes in a
+# [P][K][2] device tensor laid out as the pilot symbols.
+SET_SLAB, SET_PLANE, SET_UPPER, SET_LOWER = 0, 1, 2, 3
 
 
 class _CModel(ctypes.Structure):
@@ -143,6 +147,13 @@ def library() -> ctypes.CDLL:
         L.apsm_track.restype = i32
         L.apsm_shutdown.argtypes = []
         L.apsm_shutdown.restype = None
+        L.apsm_ball_workspace_bytes.argtypes = [i32, i32, i32]
+        L.apsm_ball_workspace_bytes.restype = ctypes.c_size_t
+        L.apsm_project_ball.argtypes = [ctypes.POINTER(_CModel), f32, f32, f32, f32, vp, ctypes.c_size_t, vp, vp]
+        L.apsm_project_ball.restype = i32
+        L.apsm_pocs.argtypes = [ctypes.POINTER(_CParams), i32, i32, i32, vp, vp, ctypes.POINTER(_CModel), f32,
+                                i32, vp, ctypes.c_size_t, vp]
+        L.apsm_pocs.restype = i32
         _lib = L
     return _lib
 
@@ -163,6 +174,7 @@ class Params:
     pos_weights: Optional[Sequence[float]] = None
     init: str = "zero"               # "zero" | "linear" (f_0 = the model's w) | "continue"
     weights: str = "position"        # "position" | "violation"
+    set_types: object = None         # uint8 device tensor [P][K][2] of SET_* codes, None: hyperslabs
 
     def _c(self):
         pw = None
@@ -170,8 +182,14 @@ class Params:
         if self.pos_weights is not None:
             keep = (ctypes.c_float * len(self.pos_weights))(*[float(x) for x in self.pos_weights])
             pw = ctypes.cast(keep, ctypes.POINTER(ctypes.c_float))
+        st = None
+        if self.set_types is not None:
+            t = self.set_types
+            if not (t.is_cuda and t.dtype == _torch().uint8 and t.is_contiguous() and t.shape[-1] == 2):
+                raise TypeError("set_types must be a contiguous uint8 device tensor [..][P][K][2]")
+            st = t.data_ptr()
         p = _CParams(self.sigma2, self.eps, self.mu, self.w_lin, self.w_gauss,
-                     int(self.window), int(self.dict_cap), INIT[self.init], pw, WEIGHTS[self.weights], 0)
+                     int(self.window), int(self.dict_cap), INIT[self.init], pw, WEIGHTS[self.weights], 0, st)
         return p, keep
 
 
@@ -270,6 +288,60 @@ def linear_mmse(h, n0: float, w=None, stream=None):
     return w[0] if squeeze else w
 
 
+def ball_workspace(model: "Model"):
+    """A device workspace for project_ball / pocs with this model's shape."""
+    torch = _torch()
+    n = library().apsm_ball_workspace_bytes(model.M2, model.K, model.dict_cap)
+    if n == 0:
+        raise APSMError(ERR_UNSUPPORTED, "apsm_ball_workspace_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=model.dict.device)
+
+
+def project_ball(model: "Model", radius: float, params: Params, workspace=None, norms=None, stream=None):
+    """Project every user's filter onto {f : ||f_k||_H <= radius}
+    (apsm_project_ball, with params' sigma2, w_lin and w_gauss).  Returns the
+    norms before the projection, a [K] float32 device tensor."""
+    torch = _torch()
+    if workspace is None:
+        workspace = ball_workspace(model)
+    if norms is None:
+        norms = torch.empty(model.K, dtype=torch.float32, device=model.dict.device)
+    _check(norms, torch.float32, (model.K,), "norms")
+    m = model._c()
+    rc = library().apsm_project_ball(ctypes.byref(m), float(params.sigma2), float(params.w_lin),
+                                     float(params.w_gauss), float(radius), workspace.data_ptr(),
+                                     workspace.numel(), norms.data_ptr(), _stream_handle(stream))
+    if rc:
+        raise APSMError(rc, "apsm_project_ball")
+    return norms
+
+
+def pocs(rx_pilot, sym_pilot, params: Params, radius: float, cycles: int, model: Optional["Model"] = None,
+         workspace=None, stream=None) -> "Model":
+    """Cyclic projections (apsm_pocs): `cycles` times the windowed parallel
+    projections over the pilots' sets, then the projection onto the ball."""
+    torch = _torch()
+    P, M2 = rx_pilot.shape
+    K = sym_pilot.shape[1]
+    _check(rx_pilot, torch.float32, (P, M2), "rx_pilot")
+    _check(sym_pilot, torch.float32, (P, K, 2), "sym_pilot")
+    if params.set_types is not None:
+        _check(params.set_types, torch.uint8, (P, K, 2), "set_types")
+    if model is None:
+        model = Model(M2, K, params.dict_cap, rx_pilot.device, params.sigma2)
+    if workspace is None:
+        workspace = ball_workspace(model)
+    cp, keep = params._c()
+    m = model._c()
+    rc = library().apsm_pocs(ctypes.byref(cp), M2, K, P, rx_pilot.data_ptr(), sym_pilot.data_ptr(),
+                             ctypes.byref(m), float(radius), int(cycles), workspace.data_ptr(), workspace.numel(),
+                             _stream_handle(stream))
+    del keep
+    if rc:
+        raise APSMError(rc, "apsm_pocs")
+    return model
+
+
 def track(model: "Model", rx, params: Params, modulation="qpsk", truth=None, decided=None, hard=None,
           errors=None, stream=None):
     """Decision-directed tracking of one block (apsm_track): detect rx
@@ -308,6 +380,8 @@ def train(rx_pilot, sym_pilot, params: Params, model: Optional[Model] = None, st
     K = sym_pilot.shape[1]
     _check(rx_pilot, torch.float32, (P, M2), "rx_pilot")
     _check(sym_pilot, torch.float32, (P, K, 2), "sym_pilot")
+    if params.set_types is not None:
+        _check(params.set_types, torch.uint8, (P, K, 2), "set_types")
     if model is None:
         model = Model(M2, K, params.dict_cap, rx_pilot.device, params.sigma2)
     model.sigma2 = float(params.sigma2)
@@ -348,6 +422,8 @@ def train_batched(rx_pilot, sym_pilot, params: Params, models=None, stream=None)
     K = sym_pilot.shape[2]
     _check(rx_pilot, torch.float32, (n, P, M2), "rx_pilot")
     _check(sym_pilot, torch.float32, (n, P, K, 2), "sym_pilot")
+    if params.set_types is not None:
+        _check(params.set_types, torch.uint8, (n, P, K, 2), "set_types")
     if models is None:
         models = [Model(M2, K, params.dict_cap, rx_pilot.device, params.sigma2) for _ in range(n)]
     if len(models) != n:

@@ -159,6 +159,7 @@ int train_impl(const apsm_params_t* p, int M2, int K, int P, int n_inst, const f
     const int nb = n_inst - b0 < apsm::kMaxTrainBatch ? n_inst - b0 : apsm::kMaxTrainBatch;
     a.rx = rx_pilot + (size_t)b0 * P * M2;
     a.sym = sym_pilot + (size_t)b0 * P * K * 2;
+    a.st = p->set_types ? p->set_types + (size_t)b0 * P * K * 2 : nullptr;
     a.n_inst = nb;
     for (int i = 0; i < nb; ++i) {
       a.dict[i] = models[b0 + i].dict;

@@ -19,6 +19,7 @@ constexpr int kMaxTrainBatch = 32;
 // Initial filter and set weights of a training (apsm_params_t.init, .weights).
 enum { kInitZero = APSM_INIT_ZERO, kInitLinear = APSM_INIT_LINEAR, kInitContinue = APSM_INIT_CONTINUE };
 enum { kWeightsPosition = APSM_WEIGHTS_POSITION, kWeightsViolation = APSM_WEIGHTS_VIOLATION };
+enum { kSetSlab = APSM_SET_SLAB, kSetPlane = APSM_SET_PLANE, kSetUpper = APSM_SET_UPPER, kSetLower = APSM_SET_LOWER };
 
 // Parameters shared by every detector of a training launch.
 struct TrainCommon {
@@ -46,6 +47,7 @@ struct TrainJob {
   // kw[n * W + q] = K(r_n, r_{n-q}) = wL r_n.r_{n-q} + wG kappa_G(r_n, r_{n-q}).
   float* glag;
   float* kw;
+  const uint8_t* st;      // [P][Kt][2] set kinds (APSM_SET_*) or null for hyperslabs
 };
 
 // Training launch of n_inst detectors of one shape, all by value (kernel
@@ -56,6 +58,7 @@ struct TrainArgs {
   TrainCommon cm;
   const float* rx;        // [n][P][M2]
   const float* sym;       // [n][P][K][2]
+  const uint8_t* st;      // [n][P][K][2] set kinds or null
   float* dict[kMaxTrainBatch];
   float* alpha[kMaxTrainBatch];
   float* w[kMaxTrainBatch];

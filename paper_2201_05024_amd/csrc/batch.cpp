@@ -358,6 +358,7 @@ int apsm_batch_create(const apsm_params_t* params, const apsm_batch_item_t* item
   pc.dict_cap = pc.window;         // per item
   if (int rc = check_params(&pc)) return rc;
   if (pc.init == APSM_INIT_CONTINUE) return APSM_ERR_UNSUPPORTED;   // kernel rows cover the pilots only
+  if (pc.set_types) return APSM_ERR_UNSUPPORTED;                     // hyperslabs only
   for (int i = 0; i < n; ++i)
     if (int rc = check_item(items[i], params->window)) return rc;
   if (!buffers_disjoint(std::vector<apsm_batch_item_t>(items, items + n))) return APSM_ERR_INVALID_ARG;

@@ -129,6 +129,7 @@ int apsm_track(const apsm_params_t* p, const apsm_model_t* model, int S, const f
                float* decided, uint8_t* hard, const uint8_t* truth, int64_t* err_count, void* stream) {
   using namespace apsm;
   if (int rc = check_params(p)) return rc;
+  if (p->set_types) return APSM_ERR_UNSUPPORTED;     // the targets are decisions: hyperslabs
   if (int rc = check_model(model)) return rc;
   if (model->dict_cap != p->dict_cap) return APSM_ERR_SHAPE;
   if (!(p->w_lin > 0.0f)) return APSM_ERR_INVALID_ARG;

@@ -141,13 +141,14 @@ struct Lds {
   float* qs;     // [W+1]    mu / (omega_0 + .. + omega_{L-1}) for |J_n| = L
   float* vb;     // [W][KP]  beta of the current step (violation weights)
   float* vd;     // [W][KP]  slab distances of the current step (violation weights)
+  int* stw;      // [W][KP]  set kinds of the window members (typed training)
   float* alds;   // [KP][cap] Gaussian coefficients, k-major (model-buffer path with SLOTS == 0)
 };
 
 __host__ __device__ inline size_t lds_floats(int W, int KP, int M2P) {
   const size_t R = W + 1;
   return 2 * R * R + (size_t)W * (W > 1 ? W - 1 : 1) + 2 * (size_t)W * KP + 2 * (size_t)W * CS + W +
-         2 * R * M2P + kWaves * KP + KP + W + (W + 1) + 2 * (size_t)W * KP;
+         2 * R * M2P + kWaves * KP + KP + W + (W + 1) + 3 * (size_t)W * KP;
 }
 
 // LDS budget of one training workgroup (one per CU; static LDS aside).
@@ -170,6 +171,7 @@ __device__ inline Lds carve(float* base, int W, int KP, int M2P) {
   s.qs = p; p += W + 1;
   s.vb = p; p += W * KP;
   s.vd = p; p += W * KP;
+  s.stw = reinterpret_cast<int*>(p); p += W * KP;
   s.alds = p;
   return s;
 }
@@ -286,6 +288,9 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   gint* const state = to_global(j.state);
   const gfloat* const glag = to_global(j.glag);
   const gfloat* const kwg = to_global(j.kw);
+  // Set kinds of the samples (generic engine) or hyperslabs throughout.
+  const bool typed = j.st != nullptr;
+  const auto stg = to_global(j.st);
   int& block_flags = *block_flags_p;
 
   for (int i = tid; i < W * KP; i += kThreads) {
@@ -387,12 +392,14 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   // user mask are applied where the value is stored), so that the waits the
   // compiler places for each value cover only that value's load.
   float comp_nx = 0.0f, comp_sg = 0.0f, bv = 0.0f, bv_nx = 0.0f;
+  int stv = kSetSlab, stv_nx = kSetSlab;
   if (tid < M2P) {
     const float c0 = sample_comp(rx, M2, M, 0, tid);
     s.rwin[tid] = c0;
     s.rwin[R * M2P + tid] = c0;
   }
   bv = sym[(k0 + (tid < K ? tid : 0)) * 2];
+  if (typed) stv = stg[(k0 + (tid < K ? tid : 0)) * 2];
 
   // Rows training: the kernel values of the even steps are loaded into
   // kr0 / kw0, those of the odd steps into kr1 / kw1, each two steps ahead
@@ -428,6 +435,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       comp_nx = rx[(size_t)(n1 >> 1) * M2 + (odd ? (m < M ? m + M : m - M) : m)];
       comp_sg = tid < M2 ? (odd && m >= M ? -1.0f : 1.0f) : 0.0f;
       bv_nx = sym[((size_t)(n1 >> 1) * Kt + k0 + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
+      if (typed) stv_nx = stg[((size_t)(n1 >> 1) * Kt + k0 + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
     }
 
     // ------------------------------------------------------------ phase A
@@ -456,7 +464,10 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     const bool evicting = ng >= cap;
     const int L = n + 1 < W ? n + 1 : W;    // |J_n| (the window is local)
     const int evlo = ng - cap + 1;          // oldest entry in the dictionary after the append
-    if (tid < KP) s.bwin[nw * KP + tid] = tid < K ? bv : 0.0f;
+    if (tid < KP) {
+      s.bwin[nw * KP + tid] = tid < K ? bv : 0.0f;
+      if (typed) s.stw[nw * KP + tid] = stv;
+    }
     if constexpr (ROWS) {
       // Gram entries of r_n against the window members, one lag per thread
       if (tid < L) {
@@ -682,14 +693,27 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       const float eupd = evicting ? eold - aev * ev : eold;
       const float e = p == 0 ? esum : eupd;
       const float x = e - bw;
-      const float beta = -soft_threshold(x, cm.eps) * ik;
+      // e minus the nearest value the member's set admits: eqn:beta's soft
+      // threshold for a hyperslab; one-sided for a halfspace; all of x for
+      // a hyperplane
+      float res;
+      if (typed) {
+        const int kind = s.stw[jw * KP + k];
+        res = kind == kSetPlane   ? x
+              : kind == kSetUpper ? fmaxf(x - cm.eps, 0.0f)
+              : kind == kSetLower ? fminf(x + cm.eps, 0.0f)
+                                  : soft_threshold(x, cm.eps);
+      } else {
+        res = soft_threshold(x, cm.eps);
+      }
+      const float beta = -res * ik;
       if (k < K) {
         s.e[jw * KP + k] = e;
         if (!isfinite(x)) flags |= 1;
       }
       if (vweights) {
         s.vb[p * KP + k] = beta;
-        s.vd[p * KP + k] = k < K ? fmaxf(fabsf(x) - cm.eps, 0.0f) : 0.0f;
+        s.vd[p * KP + k] = k < K ? fabsf(res) : 0.0f;
       } else {
         commit(p, k, jw, slot, k < K ? qscale * om * beta : 0.0f, aold);
       }
@@ -761,6 +785,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     // W-rows rings are read only in phase C), so no barrier is needed here.
 
     bv = bv_nx;
+    stv = stv_nx;
     sn = sn + 1 == cap ? 0 : sn + 1;
     nw = nw + 1 == W ? 0 : nw + 1;
     nr = nr + 1 == R ? 0 : nr + 1;
@@ -843,6 +868,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs a) {
   TrainJob j;
   j.rx = a.rx + (size_t)b * a.P * a.M2;
   j.sym = a.sym + (size_t)b * a.P * a.K * 2;
+  j.st = a.st ? a.st + (size_t)b * a.P * a.K * 2 : nullptr;
   j.dict = a.dict[b];
   j.alpha = a.alpha[b];
   j.w = a.w[b];

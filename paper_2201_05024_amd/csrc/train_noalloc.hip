@@ -67,6 +67,7 @@ int apsm_train_noalloc(const apsm_params_t* p, int M2, int K, int P, const float
                        const apsm_model_t* model, void* stream) {
   using namespace apsm;
   if (int rc = check_params(p)) return rc;
+  if (p->set_types) return APSM_ERR_UNSUPPORTED;
   if (p->init == APSM_INIT_CONTINUE) return APSM_ERR_UNSUPPORTED;   // kernel rows cover the pilots only
   if (!rx_pilot || !sym_pilot || !model) return APSM_ERR_INVALID_ARG;
   if (P < 1 || M2 < 2 || (M2 & 1) || K < 1) return APSM_ERR_SHAPE;

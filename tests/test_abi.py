@@ -399,3 +399,78 @@ def test_mmse_and_track_validation():
     assert L.apsm_track(ctypes.byref(_params(dict_cap=300)), ctypes.byref(m), 10, 1, 2, 1, None, None, None,
                         None) == 2
     assert L.apsm_track(ctypes.byref(p), ctypes.byref(m), 10, 1, 2, 1, None, 1, None, None) == 1   # truth w/o count
+
+
+# ------------------------------------------------ generic projection engine
+
+def _al(x):
+    return (x + 255) & ~255
+
+
+@needs_lib
+def test_ball_workspace_bytes():
+    L = A.library()
+    for M2, K, cap in ((32, 6, 1024), (128, 16, 8192), (2, 1, 1), (6, 3, 70)):
+        want = _al(cap * M2 * 4) + _al(cap * K * 8) + _al(K * 4)
+        assert L.apsm_ball_workspace_bytes(M2, K, cap) == want
+    for bad in ((3, 1, 10), (0, 1, 10), (32, 0, 10), (32, 17, 10), (256, 1, 10), (32, 1, 0)):
+        assert L.apsm_ball_workspace_bytes(*bad) == 0
+
+
+@needs_lib
+def test_project_ball_rejects_bad_args():
+    L = A.library()
+    m = _model(M2=32, K=6, cap=256)
+    need = L.apsm_ball_workspace_bytes(32, 6, 256)
+    ws = 1 << 20                          # an aligned stand-in address; nothing is launched
+
+    def call(model=m, sigma2=0.5, wl=0.5, wg=0.5, radius=1.0, ws=ws, nb=need):
+        return L.apsm_project_ball(ctypes.byref(model) if model is not None else None, sigma2, wl, wg, radius,
+                                   ws, nb, None, None)
+
+    assert call(model=None) == A.ERR_INVALID_ARG
+    assert call(model=_model(M2=7)) == A.ERR_SHAPE
+    assert call(sigma2=0.0) == A.ERR_INVALID_ARG
+    assert call(wl=0.0, wg=0.0) == A.ERR_INVALID_ARG
+    assert call(wl=-1.0) == A.ERR_INVALID_ARG
+    assert call(radius=-1.0) == A.ERR_INVALID_ARG
+    assert call(radius=float("nan")) == A.ERR_INVALID_ARG
+    assert call(radius=float("inf")) == A.ERR_INVALID_ARG
+    assert call(ws=None) == A.ERR_WORKSPACE
+    assert call(nb=need - 1) == A.ERR_WORKSPACE
+    assert call(ws=ws + 16) == A.ERR_WORKSPACE            # not 256-byte aligned
+
+
+@needs_lib
+def test_pocs_rejects_bad_args():
+    L = A.library()
+    m = _model(M2=32, K=6, cap=256)
+    need = L.apsm_ball_workspace_bytes(32, 6, 256)
+    ws = 1 << 20
+
+    def call(p=None, M2=32, K=6, P=64, rx=1, sym=1, model=m, radius=1.0, cycles=2, ws=ws, nb=need):
+        p = p if p is not None else _params()
+        return L.apsm_pocs(ctypes.byref(p), M2, K, P, rx, sym, ctypes.byref(model), radius, cycles, ws, nb, None)
+
+    assert call(cycles=0) == A.ERR_INVALID_ARG
+    assert call(p=_params(w_lin=0.0, w_gauss=1.0), cycles=2) == A.ERR_INVALID_ARG   # continued cycles need wL > 0
+    assert call(p=_params(mu=2.5)) == A.ERR_INVALID_ARG
+    assert call(radius=-0.5) == A.ERR_INVALID_ARG
+    assert call(nb=need - 256) == A.ERR_WORKSPACE
+    assert call(rx=None) == A.ERR_INVALID_ARG
+    assert call(P=0) == A.ERR_SHAPE
+    assert call(model=_model(M2=32, K=6, cap=300)) == A.ERR_SHAPE        # capacity differs from params
+    assert call(K=5) == A.ERR_SHAPE
+
+
+@needs_lib
+def test_set_types_only_where_supported():
+    """Entry points that train on hyperslabs only reject set kinds."""
+    L = A.library()
+    p = _params(set_types=1 << 20)
+    m = _model()
+    assert L.apsm_train_noalloc(ctypes.byref(p), 32, 6, 64, 1, 1, ctypes.byref(m), None) == A.ERR_UNSUPPORTED
+    assert L.apsm_track(ctypes.byref(p), ctypes.byref(m), 10, 1, 2, 1, None, None, None, None) == A.ERR_UNSUPPORTED
+    item = A._CBatchItem(model=_model(), sigma2=0.5, P=64, rx_pilot=1, sym_pilot=1, S=0, modulation=0)
+    h = ctypes.c_void_p()
+    assert L.apsm_batch_create(ctypes.byref(p), ctypes.byref(item), 1, ctypes.byref(h)) == A.ERR_UNSUPPORTED
