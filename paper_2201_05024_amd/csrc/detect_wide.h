@@ -62,9 +62,10 @@ __host__ __device__ constexpr int m2p_wide(int m2) { return m2 <= 32 ? 32 : m2 <
 template <int M2P>
 struct Geo {
   static constexpr int NB = M2P / 32;          // 32-deep component blocks
-  static constexpr int RH = 2 * M2P + 8;       // halves per dictionary row: d_hi | d_lo | pad
-  static constexpr int RB = RH * 2;            // row bytes; dwords = 4 (mod 8): conflict-free b128 reads
-  static constexpr int D_BYTES = kStage * RB;  // the stage's rows
+  // The stage's entries as MFMA A fragments: per (block, row tile, component
+  // block, hi/lo) one KiB, lane l's eight halves at 16 l (one conflict-free
+  // ds_read_b128 per wave).
+  static constexpr int D_BYTES = 2 * 2 * NB * 2 * 1024;
   static constexpr int A_BYTES = 2 * 2048;     // per block: coefficients^T hi (1 KiB), then lo (1 KiB)
   static constexpr int N_BYTES = 1024;         // squared norms: per block [g][8] floats, padded
   static constexpr int STAGE_BYTES = D_BYTES + A_BYTES + N_BYTES;
@@ -223,6 +224,18 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
     // the other buffer was last read in stage c - 1, which every wave has left
     if (c + 1 < nst) stage_async<M2P>(packed, c + 1, lds + ((c + 1) & 1) * G::STAGE_BYTES, wave, lane);
     const unsigned char* st = lds + (c & 1) * G::STAGE_BYTES;
+    // The A fragments of each (row tile, component block) group are read
+    // one group ahead (two register buffers), so that the LDS latency of a
+    // group is covered by the previous group's matrix instructions.
+    constexpr int NG = 2 * NB;               // (row tile, component block) groups per 32-entry block
+    half8 pdh[2], pdl[2];
+    auto load_group = [&](int blk, int gi, int buf) {
+      const int rt = gi / NB, jb = gi % NB;
+      const unsigned char* fr = st + (((blk * 2 + rt) * NB + jb) * 2) * 1024 + lane * 16;
+      pdh[buf] = *reinterpret_cast<const half8*>(fr);
+      pdl[buf] = *reinterpret_cast<const half8*>(fr + 1024);
+    };
+    load_group(0, 0, 0);
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
       const float* nb = reinterpret_cast<const float*>(st + G::D_BYTES + G::A_BYTES + blk * 128) + 8 * g;
@@ -232,20 +245,18 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
       const half8 al = *reinterpret_cast<const half8*>(st + G::D_BYTES + blk * 2048 + 1024 + lane * 16);
       floatx4 acc1[NS][2];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        const _Float16* row =
-            reinterpret_cast<const _Float16*>(st + (blk * 32 + rt * 16 + col) * G::RB) + 8 * g;
+      for (int gi = 0; gi < NG; ++gi) {
+        const int cur = (blk * NG + gi) & 1;
+        if (gi + 1 < NG) load_group(blk, gi + 1, cur ^ 1);
+        else if (blk == 0) load_group(1, 0, cur ^ 1);
+        const int rt = gi / NB, jb = gi % NB;
+        const half8 dh = pdh[cur], dl = pdl[cur];
 #pragma unroll
-        for (int jb = 0; jb < NB; ++jb) {
-          const half8 dh = *reinterpret_cast<const half8*>(row + 32 * jb);
-          const half8 dl = *reinterpret_cast<const half8*>(row + M2P + 32 * jb);
-#pragma unroll
-          for (int t = 0; t < NS; ++t) {
-            floatx4 c0 = jb == 0 ? cinit[t] : acc1[t][rt];
-            c0 = mfma(dh, xh[t][jb], c0);
-            c0 = mfma(dl, xh[t][jb], c0);
-            acc1[t][rt] = mfma(dh, xl[t][jb], c0);
-          }
+        for (int t = 0; t < NS; ++t) {
+          floatx4 c0 = jb == 0 ? cinit[t] : acc1[t][rt];
+          c0 = mfma(dh, xh[t][jb], c0);
+          c0 = mfma(dl, xh[t][jb], c0);
+          acc1[t][rt] = mfma(dh, xl[t][jb], c0);
         }
       }
       const float cn[8] = {mc2 * n0[0], mc2 * n0[1], mc2 * n0[2], mc2 * n0[3],

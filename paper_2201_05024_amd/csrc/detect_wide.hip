@@ -7,7 +7,12 @@
 //   weights  w_k scaled by 2^e_w as the A operand of the linear contraction:
 //            hi halves [jb][g][u][8], then lo halves (u the user, padded to
 //            16; component 32 jb + 8 g + i);
-//   stages   per 64 entries: the rows [64][d_hi | d_lo | pad] (2^e_d d),
+//   stages   per 64 entries: the entries (2^e_d d) as the A fragments of
+//            the distance contraction, per (32-entry block, 16-entry row
+//            tile, 32-component block) a KiB of hi halves then a KiB of lo
+//            halves, lane 16 g + r holding components 8 g .. 8 g + 7 of the
+//            tile's row r (the LDS image: one conflict-free ds_read_b128
+//            per wave and fragment),
 //            per 32-entry block the coefficients^T (2^e_a alpha) hi then lo
 //            as [g][u][8] in the block's contraction order, then the squared
 //            norms ||d||^2 (unscaled FP32) per block as [g][8], padded to 1 KiB.
@@ -99,9 +104,11 @@ __device__ __forceinline__ void pack_entry(const float* dict, const float* alpha
   const bool valid = e < D && e < cap;
   const int s = e / kStage, r = e % kStage, blk = r / 32, q = r % 32;
   unsigned char* st = out + kHeader + G::W_BYTES + (size_t)s * G::STAGE_BYTES;
-  // the row, assembled eight halves at a time and written with 16-byte stores
+  // the entry's A fragments, eight halves at a time (16-byte stores): entry
+  // q of block blk is row q % 16 of row tile q / 16; components 32 jb + 8 g
+  // + 0..7 go to lane 16 g + q % 16 of fragment (blk, tile, jb)
   const float scd = ldexpf(1.0f, hdr[0]);
-  auto row = gmem(reinterpret_cast<half8*>(st + r * G::RB));
+  const int rt = q >> 4, rc = q & 15;
   float n = 0.0f;
 #pragma unroll
   for (int m0 = 0; m0 < M2P; m0 += 8) {
@@ -116,13 +123,11 @@ __device__ __forceinline__ void pack_entry(const float* dict, const float* alpha
       hv[v] = hi;
       lv[v] = lo;
     }
-    row[m0 / 8] = hv;
-    row[(M2P + m0) / 8] = lv;
+    const int jb = m0 >> 5, gq = (m0 >> 3) & 3;
+    auto fr = gmem(reinterpret_cast<half8*>(st + (((blk * 2 + rt) * NB + jb) * 2) * 1024));
+    fr[gq * 16 + rc] = hv;
+    fr[64 + gq * 16 + rc] = lv;
   }
-  half8 zero8;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) zero8[v] = (_Float16)0.0f;
-  row[2 * M2P / 8] = zero8;
   // contraction position of this entry in its block: entry 4 g + i (i < 4)
   // or 16 + 4 g + (i - 4)
   const int g = (q & 15) >> 2, i = (q & 3) + (q >= 16 ? 4 : 0);

@@ -137,9 +137,10 @@ def test_packed_bytes():
     L.apsm_model_packed_bytes.restype = ctypes.c_size_t
     def wide(m2p, cap):
         # two-contraction layout: 256-byte header, the linear weights (2M/32 x
-        # 2 KiB), stages of 64 entries: rows of (2 * 2M + 8) halves, 4 KiB of
+        # 2 KiB), stages of 64 entries: the entries' hi and lo halves as
+        # 1 KiB MFMA fragments (64 x 2M x 2 parts x 2 bytes), 4 KiB of
         # coefficients, 1 KiB of norms
-        return 256 + m2p // 32 * 2048 + -(-cap // 64) * (64 * (2 * m2p + 8) * 2 + 4096 + 1024)
+        return 256 + m2p // 32 * 2048 + -(-cap // 64) * (64 * m2p * 2 * 2 + 4096 + 1024)
 
     def f16(m2p, k4, cap):
         # split-FP16 layout: 64-byte header, rows padded to 128 entries of
@@ -151,11 +152,12 @@ def test_packed_bytes():
     assert L.apsm_model_packed_bytes(32, 6, 1000) == f16(32, 8, 1000) + wide(32, 1000)
     assert f16(32, 8, 1000) == (64 + 1024 * (72 * 2 + 12 * 4) + 255) // 256 * 256
     # two-contraction layout (2M > 64 or K > 8): 256-byte header, the linear
-    # weights (2M/32 x 2 KiB), stages of 64 entries: rows of (2 * 2M + 8)
-    # halves, 4 KiB of coefficients, 1 KiB of norms
-    assert L.apsm_model_packed_bytes(128, 16, 1000) == 256 + 4 * 2048 + 16 * (64 * 528 + 4096 + 1024)
+    # weights (2M/32 x 2 KiB), stages of 64 entries: hi and lo fragments of
+    # 1 KiB (64 entries x 2M x 2 parts x 2 bytes), 4 KiB of coefficients,
+    # 1 KiB of norms
+    assert L.apsm_model_packed_bytes(128, 16, 1000) == 256 + 4 * 2048 + 16 * (32768 + 4096 + 1024)
     assert L.apsm_model_packed_bytes(128, 3, 64) == wide(128, 64)         # 2M > 64: one layout
-    assert L.apsm_model_packed_bytes(32, 9, 65) == 256 + 1 * 2048 + 2 * (64 * 144 + 4096 + 1024)
+    assert L.apsm_model_packed_bytes(32, 9, 65) == 256 + 1 * 2048 + 2 * (8192 + 4096 + 1024)
     assert L.apsm_model_packed_bytes(20, 12, 10) == L.apsm_model_packed_bytes(32, 16, 64)
     assert L.apsm_model_packed_bytes(66, 1, 10) == L.apsm_model_packed_bytes(128, 16, 64)
     # 2M = 40 runs with the 64-wide layouts: rows of 2*64+8 halves, K4 + 4 floats each
