@@ -288,9 +288,15 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
   gint* const state = to_global(j.state);
   const gfloat* const glag = to_global(j.glag);
   const gfloat* const kwg = to_global(j.kw);
-  // Set kinds of the samples (generic engine) or hyperslabs throughout.
-  const bool typed = j.st != nullptr;
-  const auto stg = to_global(j.st);
+  // Set kinds of the samples (generic engine) or hyperslabs throughout; the
+  // rows training (the batch path) takes hyperslabs only and compiles
+  // without them.  The kinds are read like the targets, unconditionally:
+  // without kinds the read goes to the symbol array (in bounds at the same
+  // byte index, the value unused), so no load of the step loop sits behind
+  // a branch.
+  constexpr bool kKinds = !ROWS;
+  const bool typed = kKinds && j.st != nullptr;
+  const auto stg = to_global(typed ? j.st : reinterpret_cast<const uint8_t*>(j.sym));
   int& block_flags = *block_flags_p;
 
   for (int i = tid; i < W * KP; i += kThreads) {
@@ -399,7 +405,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     s.rwin[R * M2P + tid] = c0;
   }
   bv = sym[(k0 + (tid < K ? tid : 0)) * 2];
-  if (typed) stv = stg[(k0 + (tid < K ? tid : 0)) * 2];
+  if constexpr (kKinds) stv = stg[(k0 + (tid < K ? tid : 0)) * 2];
 
   // Rows training: the kernel values of the even steps are loaded into
   // kr0 / kw0, those of the odd steps into kr1 / kw1, each two steps ahead
@@ -435,7 +441,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
       comp_nx = rx[(size_t)(n1 >> 1) * M2 + (odd ? (m < M ? m + M : m - M) : m)];
       comp_sg = tid < M2 ? (odd && m >= M ? -1.0f : 1.0f) : 0.0f;
       bv_nx = sym[((size_t)(n1 >> 1) * Kt + k0 + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
-      if (typed) stv_nx = stg[((size_t)(n1 >> 1) * Kt + k0 + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
+      if constexpr (kKinds) stv_nx = stg[((size_t)(n1 >> 1) * Kt + k0 + (tid < K ? tid : 0)) * 2 + (n1 & 1)];
     }
 
     // ------------------------------------------------------------ phase A
@@ -466,7 +472,7 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     const int evlo = ng - cap + 1;          // oldest entry in the dictionary after the append
     if (tid < KP) {
       s.bwin[nw * KP + tid] = tid < K ? bv : 0.0f;
-      if (typed) s.stw[nw * KP + tid] = stv;
+      if constexpr (kKinds) s.stw[nw * KP + tid] = stv;
     }
     if constexpr (ROWS) {
       // Gram entries of r_n against the window members, one lag per thread
