@@ -72,9 +72,12 @@ def detection_roofline(kernel, det_s, vectors, D, M2, K, M2P):
 # plain device copy (profiles/).  Valid only for the sources they were taken
 # with; reported as null otherwise.
 MEASURED_TRAFFIC = {
-    "bytes": int((60411863.8 * 2.0 + 17825792.2 * 1.0) * 1024),     # profiles/detect_wide_large_array_counters.md
-    "sources": {"paper_2201_05024_amd/csrc/detect_wide.h": "020c1e54e646402cd3d1ec8e7a92d4165ad3c0fe",
-                "paper_2201_05024_amd/csrc/detect_wide.hip": "ef7cba1378c10e8479e49e196a7551976ed2d250"},
+    # FETCH_SIZE + WRITE_SIZE of detect_wide_batch_kernel<128> per dispatch,
+    # both x1.000 by the 256 MiB copy of the same runs
+    # (profiles/detect_wide_large_array_counters.md)
+    "bytes": int((60942330.2 * 1.0 + 22020096.2 * 1.0) * 1024),
+    "sources": {"paper_2201_05024_amd/csrc/detect_wide.h": "f68ab1c73f6ca1a8f7822a5c5ff976534b3ac961",
+                "paper_2201_05024_amd/csrc/detect_wide.hip": "2f0f92f25462fe0d38e2031cb2fefae3a99366b2"},
 }
 
 
@@ -104,7 +107,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timings")
     ap.add_argument("--headline-only", action="store_true",
-                    help="only the large-array workload (profiling runs)")
+                    help="only the large-array workload (profiling runs); same as --extra ''")
+    ap.add_argument("--extra", default="slot,mixed,unrolled,small",
+                    help="comma list of the further workloads after the headline: "
+                         "slot, mixed, unrolled, small (default: all)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-detector forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
@@ -776,10 +782,18 @@ def main():
         "data": "synthetic (seeded Rayleigh channel, Rapp PA, AWGN), generated on the device",
     }
     out.update(head)
-    if not args.headline_only:
+    extra = set() if args.headline_only else {e for e in args.extra.split(",") if e}
+    unknown = extra - {"slot", "mixed", "unrolled", "small"}
+    if unknown:
+        print(f"bench.py: unknown workloads {sorted(unknown)}", file=sys.stderr)
+        return 2
+    if "slot" in extra:
         out["slot"] = run_slot(args, dev, s_train, s_det)
+    if "mixed" in extra:
         out["batched_mixed"] = run_batched_mixed(args, dev)
+    if "unrolled" in extra:
         out["unrolled"] = run_unrolled(dev)
+    if "small" in extra:
         out.update(run_small(dev))
     if args.copy_calibration:
         n = 64 << 20
