@@ -143,8 +143,14 @@ class APSMParams:
     # "position": q_j from the position weights (uniform 1/|J_n| without them);
     # "violation": per user k, q_kj = d_kj / sum_{i in J_n} d_ki with d_kj =
     # max(|f_n(r_j) - b_kj| - eps, 0) the distance of f_n(r_j) to its slab
-    # (0 for every member when none is violated)
+    # (0 for every member when none is violated);
+    # "active": per user k, q_kj = 1 / |A_k| on the members A_k whose set
+    # f_n violates, 0 elsewhere (no update when none is violated)
     weight_mode: str = "position"
+    # Extrapolated relaxation: per user the step mu * M_n with
+    # M_n = sum_j q_j ||P_j f - f||^2 / ||sum_j q_j (P_j f - f)||^2 >= 1
+    # (1 where the denominator vanishes)
+    extrapolate: bool = False
 
 
 class Filter:
@@ -286,7 +292,7 @@ class Trainer:
         self.p = p
         if p.dict_cap is not None and p.dict_cap < p.window:
             raise ValueError("dictionary cap must be at least the window size")
-        if p.weight_mode not in ("position", "violation"):
+        if p.weight_mode not in ("position", "violation", "active"):
             raise ValueError(p.weight_mode)
         T, M2 = self.R.shape
         K = self.B.shape[1]
@@ -318,9 +324,10 @@ class Trainer:
             else:
                 bet[j] = np.array([beta_set(e[j][k], self.B[j, k], p.eps, kjj, self.types[j, k])
                                    for k in range(f.K)])
-        if p.weight_mode == "violation":
-            # q_kj proportional to the distance of f_n(r_j) to set C_kj (the
-            # paper leaves the weights free to prioritise sets adaptively)
+        if p.weight_mode in ("violation", "active"):
+            # q_kj proportional to the distance of f_n(r_j) to set C_kj, or
+            # uniform over the violated sets (the paper leaves the weights
+            # free to prioritise sets adaptively)
             if self.types is None:
                 dist = {j: np.maximum(np.abs(e[j] - self.B[j]) - p.eps, 0.0) for j in J}
             else:
@@ -328,12 +335,26 @@ class Trainer:
                 for j in J:
                     iv = [set_interval(self.types[j, k], self.B[j, k], p.eps) for k in range(f.K)]
                     dist[j] = np.array([abs(min(max(e[j][k], lo), hi) - e[j][k]) for k, (lo, hi) in enumerate(iv)])
+            if p.weight_mode == "active":
+                dist = {j: (dist[j] > 0.0).astype(np.float64) for j in J}
             tot = sum(dist.values())
             qk = {j: np.divide(dist[j], tot, out=np.zeros(f.K), where=tot > 0) for j in J}
         else:
             qk = {j: np.full(f.K, q[j]) for j in J}
+        M = np.ones(f.K)
+        if p.extrapolate:
+            # P_j f - f = beta_j kappa(r_j, .), of squared norm beta_j^2
+            # kappa(r_j, r_j); the norm of the combination through the Gram
+            # matrix of the members
+            Jl = list(J)
+            Gm = gram(self.R[Jl], p.sigma2, p.w_lin, p.w_gauss)
+            Q = np.array([qk[j] for j in Jl])                   # [L][K]
+            Bt = np.array([bet[j] for j in Jl])
+            num = np.einsum("jk,jk,j->k", Q, Bt * Bt, np.diag(Gm))
+            den = np.einsum("jk,jl,lk->k", Q * Bt, Gm, Q * Bt)
+            M = np.where(den > 0.0, num / np.where(den > 0.0, den, 1.0), 1.0)
         for j in J:
-            c = p.mu * qk[j] * bet[j]                      # [K]
+            c = p.mu * M * qk[j] * bet[j]                  # [K]
             # P_{C_j} adds beta_j (wL kappa_L(r_j, .) + wG kappa_G(r_j, .)).
             f.w += np.outer(c * p.w_lin, self.R[j])
             f.alpha[f.slot_of(self.n0 + j)] += c * p.w_gauss

@@ -254,3 +254,126 @@ def test_violation_weights_fejer_monotone(mu, W):
         moved += int(np.any(cur < prev * (1 - 1e-6)))
         prev = cur
     assert moved > 5
+
+
+# ------------------------------------------ active-set weights, extrapolation
+
+def test_active_weights_equal_uniform_while_every_member_is_violated():
+    """Targets far from every prediction: all members violate their slabs, so
+    uniform weights over the violated sets are the uniform weights."""
+    rng = np.random.default_rng(31)
+    R = rng.standard_normal((40, 4)) * 0.5
+    B = 20.0 + rng.uniform(0, 1, (40, 2))
+    base = dict(sigma2=0.5, eps=0.05, mu=0.2, window=6)
+    a = O.Trainer(R, B, O.APSMParams(weight_mode="active", **base))
+    b = O.Trainer(R, B, O.APSMParams(**base))
+    held = 0
+    for n in range(40):
+        _, e, _ = b.step()
+        if not all(np.all(np.abs(e[j] - B[j]) > base["eps"]) for j in e):
+            break
+        a.step()
+        np.testing.assert_allclose(a.f.w, b.f.w, atol=1e-12)
+        np.testing.assert_allclose(a.f.alpha, b.f.alpha, atol=1e-12)
+        held += 1
+    assert held >= 20
+
+
+def test_active_weights_ignore_satisfied_members():
+    """A member inside its slab gets weight 0: with two members of which only
+    one is violated, the active step is that member's full projection."""
+    rng = np.random.default_rng(32)
+    R = rng.standard_normal((2, 4)) * 0.6
+    p = O.APSMParams(sigma2=0.5, eps=0.1, mu=1.0, window=2, weight_mode="active")
+    tr = O.Trainer(R, np.array([[0.0], [3.0]]), p)     # step 0: member 0 lands on its slab
+    tr.step()
+    f0 = tr.f.evaluate(R[0])[0]
+    B = np.array([[f0], [3.0]])                          # member 0 now satisfied at step 1
+    tr2 = O.Trainer(R, B, p)
+    tr2.step()
+    _, e, bet = tr2.step()
+    assert abs(e[0][0] - B[0, 0]) <= p.eps and bet[0][0] == 0.0
+    # q = (0, 1): f_{n+1}(r_1) lands on b_1 - eps
+    np.testing.assert_allclose(tr2.f.evaluate(R[1])[0], B[1, 0] - p.eps, atol=1e-12)
+
+
+def test_extrapolation_with_window_one_is_the_plain_step():
+    rng = np.random.default_rng(33)
+    R = rng.standard_normal((30, 4)) * 0.7
+    B = rng.standard_normal((30, 3))
+    a = O.train(R, B, O.APSMParams(window=1, extrapolate=True))
+    b = O.train(R, B, O.APSMParams(window=1))
+    np.testing.assert_allclose(a.w, b.w, atol=1e-13)
+    np.testing.assert_allclose(a.alpha, b.alpha, atol=1e-13)
+
+
+@pytest.mark.parametrize("mode", ["position", "active", "violation"])
+def test_extrapolation_on_orthogonal_sets_is_every_projection_at_once(mode):
+    """Gaussian part only, samples so far apart that their kernel sections are
+    orthogonal: the extrapolated step moves every violated member onto its
+    slab boundary (M_n undoes the averaging), which no averaged step does."""
+    rng = np.random.default_rng(34)
+    T, W = 24, 5
+    R = rng.standard_normal((T, 4)) * 5.0
+    B = rng.standard_normal((T, 2))
+    p = O.APSMParams(sigma2=1e-3, eps=0.05, mu=1.0, window=W, w_lin=0.0, w_gauss=1.0,
+                     extrapolate=True, weight_mode=mode)
+    G = O.gram(R, p.sigma2, 0.0, 1.0)
+    assert np.abs(G - np.eye(T)).max() < 1e-300          # orthogonal sections
+    tr = O.Trainer(R, B, p)
+    landed = 0
+    for n in range(T):
+        J, e, bet = tr.step()
+        for j in J:
+            for k in range(2):
+                if abs(e[j][k] - B[j, k]) > p.eps:
+                    target = B[j, k] + np.sign(e[j][k] - B[j, k]) * p.eps
+                    np.testing.assert_allclose(tr.f.evaluate(R[j])[k], target, atol=1e-12)
+                    landed += 1
+    assert landed > T
+
+
+@pytest.mark.parametrize("mu,mode", [(0.5, "position"), (1.0, "active"), (1.5, "violation"), (1.0, "position")])
+def test_extrapolated_iteration_is_fejer_monotone(mu, mode):
+    rng = np.random.default_rng(35)
+    T, M2, K, eps, s2 = 45, 4, 2, 0.05, 0.4
+    star = O.Filter(K, M2, s2)
+    star.w = rng.standard_normal((K, M2)) * 0.5
+    for m in range(5):
+        star.append(rng.standard_normal(M2) * 0.6, -1 - m)
+        star.alpha[-1] = rng.standard_normal(K) * 0.5
+    R = rng.standard_normal((T, M2)) * 0.6
+    B = np.array([star.evaluate(r) for r in R]) + rng.uniform(-0.9 * eps, 0.9 * eps, (T, K))
+    p = O.APSMParams(sigma2=s2, eps=eps, mu=mu, window=6, extrapolate=True, weight_mode=mode)
+    tr = O.Trainer(R, B, p)
+    prev = tr.f.h_norm2_diff(star, 0.5, 0.5)
+    moved = 0
+    for _ in range(T):
+        tr.step()
+        cur = tr.f.h_norm2_diff(star, 0.5, 0.5)
+        assert np.all(cur <= prev * (1 + 1e-10) + 1e-12)
+        moved += int(np.any(cur < prev * (1 - 1e-6)))
+        prev = cur
+    assert moved > 5
+
+
+def test_extrapolation_fejer_detects_an_overshoot():
+    """Teeth: a step of 2.5 M_n (past the admissible relaxation) breaks Fejer."""
+    rng = np.random.default_rng(36)
+    T, M2, K, eps, s2 = 45, 4, 2, 0.05, 0.4
+    star = O.Filter(K, M2, s2)
+    star.w = rng.standard_normal((K, M2)) * 0.5
+    R = rng.standard_normal((T, M2)) * 0.6
+    B = np.array([star.evaluate(r) for r in R])
+    p = O.APSMParams(sigma2=s2, eps=eps, mu=1.0, window=6, extrapolate=True)
+    tr = O.Trainer(R, B, p)
+    prev = tr.f.h_norm2_diff(star, 0.5, 0.5)
+    broke = False
+    for _ in range(T):
+        w0 = tr.f.w.copy()
+        tr.step()
+        tr.f.w = w0 + 2.5 * (tr.f.w - w0)                 # planted mistake in the linear part
+        cur = tr.f.h_norm2_diff(star, 0.5, 0.5)
+        broke |= bool(np.any(cur > prev * (1 + 1e-6)))
+        prev = cur
+    assert broke
