@@ -88,6 +88,9 @@ extern "C" {
 #define APSM_WEIGHTS_VIOLATION  1  /* per user k, q_kj proportional to member j's distance
                                       max(|f_n(r_j) - b_kj| - eps, 0) to its slab (0 for all when
                                       none is violated); pos_weights must be NULL               */
+#define APSM_WEIGHTS_ACTIVE     2  /* per user k, q_kj uniform over the members whose set f_n
+                                      violates by more than 1e-5, 0 on the others (no update
+                                      when none is); pos_weights must be NULL                   */
 
 /* Kind of the closed convex set a training sample defines through the value
  * f(r_j) (apsm_params_t.set_types).  The hyperslab is the detector's set
@@ -118,8 +121,13 @@ extern "C" {
  *  pos_weights HOST pointer to `window` positive floats omega (omega[0] for the
  *              newest set j = n), q_j = omega[n-j] / sum_{i in J_n} omega[n-i];
  *              NULL for uniform q_j = 1/|J_n| (eqn:apsm's weights, Sec. II-D).
- *  weights     APSM_WEIGHTS_*: position weights, or weights proportional to the
- *              slab violation (Sec. II-D: the q_j may prioritise sets adaptively).
+ *  weights     APSM_WEIGHTS_*: position weights, weights proportional to the slab
+ *              violation, or uniform over the violated sets (Sec. II-D: the q_j
+ *              may prioritise sets adaptively).
+ *  extrapolate 0, or 1 for the extrapolated relaxation: per user the step
+ *              mu * M_n with M_n = sum_j q_j ||P_j f - f||^2 / ||sum_j q_j (P_j f - f)||^2
+ *              >= 1 over the window's sets (1 where the denominator vanishes);
+ *              mu stays in (0, 2).
  *  set_types   DEVICE pointer to uint8 APSM_SET_* kinds laid out as the pilot
  *              symbols, [P][K][2] (real, imaginary part; [n_inst][P][K][2] for
  *              apsm_train_batched), or NULL for hyperslabs everywhere.  With
@@ -137,7 +145,7 @@ typedef struct apsm_params {
   int32_t init;
   const float* pos_weights;
   int32_t weights;
-  int32_t reserved;           /* must be 0 */
+  int32_t extrapolate;
   const uint8_t* set_types;
 } apsm_params_t;
 

@@ -130,6 +130,11 @@ def training_sequence(rx_pilot: np.ndarray, sym_pilot: np.ndarray):
 # on a dictionary of received vectors (Sec. II-D, last paragraph)
 # --------------------------------------------------------------------------
 
+# Distance to its set above which a member counts as violated for the
+# active-set weights (a reading; see APSMParams.weight_mode).
+ACTIVE_MARGIN = 1e-5
+
+
 @dataclass
 class APSMParams:
     sigma2: float = 0.5
@@ -145,7 +150,9 @@ class APSMParams:
     # max(|f_n(r_j) - b_kj| - eps, 0) the distance of f_n(r_j) to its slab
     # (0 for every member when none is violated);
     # "active": per user k, q_kj = 1 / |A_k| on the members A_k whose set
-    # f_n violates, 0 elsewhere (no update when none is violated)
+    # f_n violates by more than ACTIVE_MARGIN, 0 elsewhere (no update when
+    # none is); the margin keeps a member that its own projection left on
+    # the boundary out of the set, whatever the rounding
     weight_mode: str = "position"
     # Extrapolated relaxation: per user the step mu * M_n with
     # M_n = sum_j q_j ||P_j f - f||^2 / ||sum_j q_j (P_j f - f)||^2 >= 1
@@ -336,7 +343,7 @@ class Trainer:
                     iv = [set_interval(self.types[j, k], self.B[j, k], p.eps) for k in range(f.K)]
                     dist[j] = np.array([abs(min(max(e[j][k], lo), hi) - e[j][k]) for k, (lo, hi) in enumerate(iv)])
             if p.weight_mode == "active":
-                dist = {j: (dist[j] > 0.0).astype(np.float64) for j in J}
+                dist = {j: (dist[j] > ACTIVE_MARGIN).astype(np.float64) for j in J}
             tot = sum(dist.values())
             qk = {j: np.divide(dist[j], tot, out=np.zeros(f.K), where=tot > 0) for j in J}
         else:

@@ -39,12 +39,12 @@ class _CParams(ctypes.Structure):
                 ("w_lin", ctypes.c_float), ("w_gauss", ctypes.c_float),
                 ("window", ctypes.c_int32), ("dict_cap", ctypes.c_int32),
                 ("init", ctypes.c_int32), ("pos_weights", ctypes.POINTER(ctypes.c_float)),
-                ("weights", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("weights", ctypes.c_int32), ("extrapolate", ctypes.c_int32),
                 ("set_types", ctypes.c_void_p)]
 
 
 INIT = {"zero": 0, "linear": 1, "continue": 2}
-WEIGHTS = {"position": 0, "violation": 1}
+WEIGHTS = {"position": 0, "violation": 1, "active": 2}
 # Set kinds of the training samples (APSM_SET_*), as uint8 codes in a
 # [P][K][2] device tensor laid out as the pilot symbols.
 SET_SLAB, SET_PLANE, SET_UPPER, SET_LOWER = 0, 1, 2, 3
@@ -173,7 +173,8 @@ class Params:
     dict_cap: int = 256
     pos_weights: Optional[Sequence[float]] = None
     init: str = "zero"               # "zero" | "linear" (f_0 = the model's w) | "continue"
-    weights: str = "position"        # "position" | "violation"
+    weights: str = "position"        # "position" | "violation" | "active"
+    extrapolate: bool = False        # extrapolated relaxation mu * M_n
     set_types: object = None         # uint8 device tensor [P][K][2] of SET_* codes, None: hyperslabs
 
     def _c(self):
@@ -189,7 +190,8 @@ class Params:
                 raise TypeError("set_types must be a contiguous uint8 device tensor [..][P][K][2]")
             st = t.data_ptr()
         p = _CParams(self.sigma2, self.eps, self.mu, self.w_lin, self.w_gauss,
-                     int(self.window), int(self.dict_cap), INIT[self.init], pw, WEIGHTS[self.weights], 0, st)
+                     int(self.window), int(self.dict_cap), INIT[self.init], pw, WEIGHTS[self.weights],
+                     int(bool(self.extrapolate)), st)
         return p, keep
 
 

@@ -38,12 +38,14 @@ int check_params(const apsm_params_t* p) {
   if (!std::isfinite(p->w_lin) || !std::isfinite(p->w_gauss) || p->w_lin < 0.0f ||
       p->w_gauss < 0.0f || (p->w_lin == 0.0f && p->w_gauss == 0.0f))
     return APSM_ERR_INVALID_ARG;
-  if (p->reserved != 0 || p->window < 1) return APSM_ERR_INVALID_ARG;
+  if ((p->extrapolate != 0 && p->extrapolate != 1) || p->window < 1) return APSM_ERR_INVALID_ARG;
   if (p->init != APSM_INIT_ZERO && p->init != APSM_INIT_LINEAR && p->init != APSM_INIT_CONTINUE)
     return APSM_ERR_INVALID_ARG;
   if (p->init != APSM_INIT_ZERO && !(p->w_lin > 0.0f)) return APSM_ERR_INVALID_ARG;   // w = wL v
-  if (p->weights != APSM_WEIGHTS_POSITION && p->weights != APSM_WEIGHTS_VIOLATION) return APSM_ERR_INVALID_ARG;
-  if (p->weights == APSM_WEIGHTS_VIOLATION && p->pos_weights) return APSM_ERR_INVALID_ARG;
+  if (p->weights != APSM_WEIGHTS_POSITION && p->weights != APSM_WEIGHTS_VIOLATION &&
+      p->weights != APSM_WEIGHTS_ACTIVE)
+    return APSM_ERR_INVALID_ARG;
+  if (p->weights != APSM_WEIGHTS_POSITION && p->pos_weights) return APSM_ERR_INVALID_ARG;
   if (p->window > APSM_MAX_WINDOW) return APSM_ERR_UNSUPPORTED;
   if (p->dict_cap < p->window) return APSM_ERR_INVALID_ARG;
   if (p->pos_weights) {
@@ -61,6 +63,7 @@ void fill_common(const apsm_params_t* p, TrainCommon& cm) {
   cm.wg = p->w_gauss;
   cm.init = p->init;
   cm.weights = p->weights;
+  cm.extrapolate = p->extrapolate;
   for (int i = 0; i < APSM_MAX_WINDOW; ++i) cm.omega[i] = 1.0f;
   if (p->pos_weights)
     for (int i = 0; i < p->window; ++i) cm.omega[i] = p->pos_weights[i];

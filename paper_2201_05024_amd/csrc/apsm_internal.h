@@ -18,7 +18,8 @@ constexpr int kMaxTrainBatch = 32;
 
 // Initial filter and set weights of a training (apsm_params_t.init, .weights).
 enum { kInitZero = APSM_INIT_ZERO, kInitLinear = APSM_INIT_LINEAR, kInitContinue = APSM_INIT_CONTINUE };
-enum { kWeightsPosition = APSM_WEIGHTS_POSITION, kWeightsViolation = APSM_WEIGHTS_VIOLATION };
+enum { kWeightsPosition = APSM_WEIGHTS_POSITION, kWeightsViolation = APSM_WEIGHTS_VIOLATION,
+       kWeightsActive = APSM_WEIGHTS_ACTIVE };
 enum { kSetSlab = APSM_SET_SLAB, kSetPlane = APSM_SET_PLANE, kSetUpper = APSM_SET_UPPER, kSetLower = APSM_SET_LOWER };
 
 // Parameters shared by every detector of a training launch.
@@ -26,7 +27,8 @@ struct TrainCommon {
   int W;                  // window size
   float eps, mu, wl, wg;
   int init;               // kInit*: f_0 = 0, the model's linear part, or the whole model continued
-  int weights;            // kWeights*: position weights (uniform by default) or violation weights
+  int weights;            // kWeights*: position weights (uniform by default), violation or active-set weights
+  int extrapolate;        // 1: extrapolated relaxation mu M_n
   float omega[APSM_MAX_WINDOW];   // position weights, omega[0] for j = n
 };
 

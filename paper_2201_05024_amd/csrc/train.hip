@@ -660,7 +660,12 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
     // proportional to member j's distance to its slab, per user): beta and
     // the distance are parked in LDS and c is formed after a barrier, once
     // the distances of all members are there.
-    const bool vweights = cm.weights == kWeightsViolation;
+    // Position weights: c = mu q_j beta at once.  Violation or active-set
+    // weights, or the extrapolated relaxation: beta and the distance to the
+    // set are parked in LDS and c is formed after a barrier (see below).
+    const bool vweights = cm.weights != kWeightsPosition;
+    const bool extra = cm.extrapolate != 0;
+    const bool two_pass = vweights || extra;
     const float qscale = s.qs[L];
     // c of member p (ring row jw, dictionary slot `slot`) and user k: the
     // coefficient ring and, on the model-buffer paths, the Gaussian
@@ -717,14 +722,69 @@ __device__ __forceinline__ void train_body(const TrainJob& j, const TrainCommon&
         s.e[jw * KP + k] = e;
         if (!isfinite(x)) flags |= 1;
       }
-      if (vweights) {
+      if (two_pass) {
         s.vb[p * KP + k] = beta;
-        s.vd[p * KP + k] = k < K ? fabsf(res) : 0.0f;
+        // active-set weights: violated by more than 1e-5 (a member that its
+        // own projection left on the boundary stays out, whatever the rounding)
+        const float dist = cm.weights == kWeightsActive ? (fabsf(res) > 1e-5f ? 1.0f : 0.0f) : fabsf(res);
+        s.vd[p * KP + k] = k < K ? dist : 0.0f;
       } else {
         commit(p, k, jw, slot, k < K ? qscale * om * beta : 0.0f, aold);
       }
     }
-    if (vweights) {
+    if (extra) {
+      // Extrapolated relaxation, per user k: c_j = mu M q_j beta_j with
+      // M = sum_j q_j beta_j^2 K_jj / sum_{j,l} u_j K_jl u_l, u = q beta
+      // (1 where the denominator is not positive).  u is parked in this
+      // step's rows of the coefficient ring (the commit overwrites them);
+      // the per-member terms replace beta and the distance in LDS and one
+      // thread per user sums them in member order.
+      __syncthreads();
+      for (int t = tid; t < L * KP; t += kThreads) {
+        const int p = t / KP, k = t - p * KP;
+        float q = 0.0f;
+        if (k < K) {
+          if (vweights) {
+            float tot = 0.0f;
+            for (int i = 0; i < L; ++i) tot += s.vd[i * KP + k];
+            q = tot > 0.0f ? s.vd[p * KP + k] / tot : 0.0f;
+          } else {
+            q = qscale * s.omega[p] / cm.mu;
+          }
+        }
+        s.c[ring_sub(nw, p, W) * CS + k] = q * s.vb[p * KP + k];
+      }
+      __syncthreads();
+      for (int t = tid; t < L * KP; t += kThreads) {
+        const int p = t / KP, k = t - p * KP;
+        const float* grow = s.gram + ring_sub(nr, p, R) * 2 * R + nr + R;   // K(r_{n-p}, r_{n-l}) at grow[-l]
+        float kt = 0.0f;
+        for (int l = 0; l < L; ++l) kt = fmaf(grow[-l], s.c[ring_sub(nw, l, W) * CS + k], kt);
+        const float u = s.c[ring_sub(nw, p, W) * CS + k];
+        s.vd[p * KP + k] = u * s.vb[p * KP + k] * grow[-p];
+        s.vb[p * KP + k] = u * kt;
+      }
+      __syncthreads();
+      if (tid < KP) {
+        float num = 0.0f, den = 0.0f;
+        for (int p = 0; p < L; ++p) {
+          num += s.vd[p * KP + tid];
+          den += s.vb[p * KP + tid];
+        }
+        s.part[tid] = den > 0.0f ? num / den : 1.0f;
+      }
+      __syncthreads();
+      for (int t = tid; t < L * KP; t += kThreads) {
+        const int p = t / KP, k = t - p * KP;
+        const int jw = ring_sub(nw, p, W);
+        const int slot = ring_sub(sn, p, cap);
+        float aold = 0.0f;
+        if constexpr (SLOTS == 0) aold = s.alds[k * cap + slot];
+        if constexpr (SLOTS < 0) aold = alpha[(size_t)slot * Kt + k0 + (k < K ? k : 0)];
+        const float c = k < K ? cm.mu * s.part[k] * s.c[jw * CS + k] : 0.0f;
+        commit(p, k, jw, slot, c, aold);
+      }
+    } else if (vweights) {
       __syncthreads();
       for (int t = tid; t < L * KP; t += kThreads) {
         const int p = t / KP, k = t - p * KP;

@@ -61,7 +61,7 @@ def _model(M2=32, K=6, cap=256, ptr=1, packed=1):
 
 def _params(**kw):
     base = dict(sigma2=0.5, eps=0.05, mu=1.0, w_lin=0.5, w_gauss=0.5, window=16, dict_cap=256,
-                init=0, pos_weights=None, weights=0, reserved=0)
+                init=0, pos_weights=None, weights=0, extrapolate=0)
     base.update(kw)
     return A._CParams(**base)
 
@@ -70,9 +70,9 @@ BAD_TRAIN = [
     (dict(sigma2=0.0), 1), (dict(sigma2=float("nan")), 1), (dict(eps=-0.1), 1),
     (dict(mu=0.0), 1), (dict(mu=2.0), 1), (dict(w_lin=0.0, w_gauss=0.0), 1),
     (dict(w_lin=-1.0), 1), (dict(window=0), 1), (dict(window=65, dict_cap=256), 3),
-    (dict(dict_cap=8, window=16), 1), (dict(reserved=1), 1),
+    (dict(dict_cap=8, window=16), 1), (dict(extrapolate=2), 1), (dict(extrapolate=-1), 1),
     (dict(init=3), 1), (dict(init=-1), 1), (dict(init=1, w_lin=0.0, w_gauss=1.0), 1),
-    (dict(init=2, w_lin=0.0, w_gauss=1.0), 1), (dict(weights=2), 1),
+    (dict(init=2, w_lin=0.0, w_gauss=1.0), 1), (dict(weights=3), 1), (dict(weights=-1), 1),
 ]
 
 
@@ -375,11 +375,19 @@ def test_weights_modes_and_init_validation():
     m = _model()
     assert L.apsm_train(ctypes.byref(_params(weights=1, pos_weights=pw)), 32, 6, 64, 1, 1, ctypes.byref(m),
                         None) == A.ERR_INVALID_ARG
+    assert L.apsm_train(ctypes.byref(_params(weights=2, pos_weights=pw)), 32, 6, 64, 1, 1, ctypes.byref(m),
+                        None) == A.ERR_INVALID_ARG
     items = (A._CBatchItem * 1)(_item())
     h = ctypes.c_void_p()
     assert L.apsm_batch_create(ctypes.byref(_params(init=2)), items, 1, ctypes.byref(h)) == 3
     assert L.apsm_train_noalloc(ctypes.byref(_params(init=2)), 32, 6, 64, 1, 1, ctypes.byref(m), None) == 3
     assert L.apsm_batch_create(ctypes.byref(_params(init=1, weights=1)), items, 1, ctypes.byref(h)) == 0
+    L.apsm_batch_destroy(h)
+    # active-set weights with the extrapolated relaxation, position weights with it
+    assert L.apsm_batch_create(ctypes.byref(_params(weights=2, extrapolate=1)), items, 1, ctypes.byref(h)) == 0
+    L.apsm_batch_destroy(h)
+    assert L.apsm_batch_create(ctypes.byref(_params(extrapolate=1, pos_weights=pw)), items, 1,
+                               ctypes.byref(h)) == 0
     L.apsm_batch_destroy(h)
 
 

@@ -202,3 +202,38 @@ def test_violation_weights(name, K, M, P, cap, W, batch):
     # different from position weights
     g = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, opar(A.Params(sigma2=0.5, window=W, dict_cap=cap)))
     assert np.abs(g.w - f.w).max() > 1e-3
+
+
+# ------------------------------------ active-set weights, extrapolated relaxation
+
+RELAX = [
+    # name, K, M, P, cap, W, batch, weights, extrapolate
+    ("register_slots", 4, 8, 150, 256, 16, False, "active", False),
+    ("register_slots", 4, 8, 150, 256, 16, False, "position", True),
+    ("register_slots", 4, 8, 150, 256, 16, False, "active", True),
+    ("lds_coefficients", 6, 16, 600, 1100, 8, False, "violation", True),
+    ("lds_coefficients", 6, 16, 600, 1100, 8, False, "active", False),
+    ("model_buffers", 16, 64, 300, 2200, 8, False, "position", True),
+    ("rows_batch", 6, 16, 300, 400, 32, True, "active", True),
+    ("rows_batch", 6, 16, 300, 400, 32, True, "position", True),
+    ("rows_batch_wrap", 3, 8, 400, 300, 16, True, "violation", True),
+]
+
+
+@pytest.mark.parametrize("name,K,M,P,cap,W,batch,weights,extrapolate", RELAX)
+def test_active_weights_and_extrapolation(name, K, M, P, cap, W, batch, weights, extrapolate):
+    announce(f"{weights} weights, extrapolate={extrapolate}, {name}")
+    inst = synth.make_instance(synth.InstanceSpec(K=K, M=M, P=P, S=300, snr_db=10.0, seed=5500 + K + W))
+    p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=W, dict_cap=cap, weights=weights, extrapolate=extrapolate)
+    if batch:
+        m = A.Model(2 * M, K, cap, DEV, 0.5)
+        A.Batch(p, [A.BatchItem(model=m, rx_pilot=cuda(inst.rx_pilot), sym_pilot=cuda(inst.sym_pilot))]).train()
+    else:
+        m = A.train(cuda(inst.rx_pilot), cuda(inst.sym_pilot), p)
+    torch.cuda.synchronize()
+    assert m.status()["flags"] == 0
+    f = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, opar(p, weight_mode=weights, extrapolate=extrapolate))
+    check_model(m, f, cap, name)
+    check_detect(m, f, inst.rx_data, "qpsk", name)
+    g = O.train_from_pilots(inst.rx_pilot, inst.sym_pilot, opar(p))
+    assert np.abs(g.w - f.w).max() > 1e-3
