@@ -35,7 +35,20 @@
 namespace apsm {
 namespace {
 
-constexpr int kT = 256;                // threads per workgroup
+constexpr int kT = 256;                // threads per workgroup (set-up, validation, reductions)
+
+// Threads of the sequential pass and reverse kernels: the per-step work is
+// spread over as many lanes as the LDS of the partial sums allows.
+template <int KP>
+constexpr int seq_threads() { return KP <= 8 ? 1024 : 512; }
+
+// The Gaussian coefficients (forward) or their adjoints (reverse), [T][KP],
+// are kept in LDS when they fit this budget, else in the workspace.
+constexpr size_t kCoefLdsMax = 64 * 1024;
+__host__ __device__ inline bool coef_in_lds(int T, int KP) { return (size_t)T * KP * sizeof(float) <= kCoefLdsMax; }
+// Their offset in the dynamic LDS (floats): after the other arrays, rounded
+// up to 16 bytes for the vector reads.
+__host__ __device__ inline size_t coef_lds_offset(size_t floats_before) { return (floats_before + 3) / 4 * 4; }
 
 __device__ __forceinline__ float comp(const float* rx, int M2, int n, int m) {
   // component m of real sample n: r_{2t} = r1(t), r_{2t+1} = r2(t) = [Im; -Re]
@@ -115,9 +128,11 @@ __global__ __launch_bounds__(kT) void unr_gram_kernel(UnrolledArgs a) {
 // or from checkpoint p0 / E.  With tape set, x and h of every step are
 // recorded (pass p at tape slot p - p0); otherwise checkpoints are written at
 // the start of every pass p with p % E == 0.
-template <int KP>
-__global__ __launch_bounds__(kT) void unr_pass_kernel(UnrolledArgs a, int p0, int p1, int tape) {
-  extern __shared__ float lds[];
+template <int KP, int NT, bool TAPE>
+__global__ __launch_bounds__(NT) void unr_pass_kernel(UnrolledArgs a, int p0, int p1) {
+  constexpr int kT = NT;
+  constexpr bool tape = TAPE;
+  extern __shared__ __attribute__((aligned(16))) float lds[];
   const int b = blockIdx.x;
   const Inst I = inst_of(a, b);
   const int T = a.T, M2 = a.M2, M2P = a.M2P, K = a.K, W = a.W;
@@ -132,7 +147,9 @@ __global__ __launch_bounds__(kT) void unr_pass_kernel(UnrolledArgs a, int p0, in
   float* zs = om + W;
   const int SW = K * M2P + T * KP;
   float* const state = tape ? I.sc : I.st;
-  float* alpha = state + K * M2P;           // [T][KP]
+  // [T][KP]: in LDS when it fits (written back to the state at the end)
+  const bool alds = coef_in_lds(T, KP);
+  float* alpha = alds ? lds + coef_lds_offset(K * M2P + 2 * WP * C * KP + W * KP + 2 * W + 1) : state + K * M2P;
   const int tid = threadIdx.x;
 
   const float sigma = a.theta[0], eps = a.theta[1], mu = a.theta[2];
@@ -168,7 +185,6 @@ __global__ __launch_bounds__(kT) void unr_pass_kernel(UnrolledArgs a, int p0, in
         for (int k = 0; k < KP; ++k) { pe[k] = 0.0f; ph[k] = 0.0f; }
         for (int i = my_c; i < T; i += C) {
           const float g = grow[i];
-          const float gd = tape ? g * drow[i] : 0.0f;
           const float4* ar = reinterpret_cast<const float4*>(alpha + (size_t)i * KP);
 #pragma unroll
           for (int q = 0; q < KP / 4; ++q) {
@@ -177,10 +193,17 @@ __global__ __launch_bounds__(kT) void unr_pass_kernel(UnrolledArgs a, int p0, in
             pe[4 * q + 1] = fmaf(v.y, g, pe[4 * q + 1]);
             pe[4 * q + 2] = fmaf(v.z, g, pe[4 * q + 2]);
             pe[4 * q + 3] = fmaf(v.w, g, pe[4 * q + 3]);
-            ph[4 * q] = fmaf(v.x, gd, ph[4 * q]);
-            ph[4 * q + 1] = fmaf(v.y, gd, ph[4 * q + 1]);
-            ph[4 * q + 2] = fmaf(v.z, gd, ph[4 * q + 2]);
-            ph[4 * q + 3] = fmaf(v.w, gd, ph[4 * q + 3]);
+          }
+          if constexpr (TAPE) {
+            const float gd = g * drow[i];
+#pragma unroll
+            for (int q = 0; q < KP / 4; ++q) {
+              const float4 v = ar[q];
+              ph[4 * q] = fmaf(v.x, gd, ph[4 * q]);
+              ph[4 * q + 1] = fmaf(v.y, gd, ph[4 * q + 1]);
+              ph[4 * q + 2] = fmaf(v.z, gd, ph[4 * q + 2]);
+              ph[4 * q + 3] = fmaf(v.w, gd, ph[4 * q + 3]);
+            }
           }
         }
         float* pp = part + ((size_t)my_s * C + my_c) * KP;
@@ -236,6 +259,8 @@ __global__ __launch_bounds__(kT) void unr_pass_kernel(UnrolledArgs a, int p0, in
     }
   }
   for (int e = tid; e < K * M2P; e += kT) state[e] = wl[e];
+  if (alds)
+    for (int e = tid; e < T * KP; e += kT) state[K * M2P + e] = alpha[e];
 }
 
 // ---------------------------------------------------------------- validation
@@ -403,9 +428,10 @@ __global__ __launch_bounds__(kT) void unr_val_bwd_kernel(UnrolledArgs a) {
 // ---------------------------------------------------------------- reverse
 // Reverse sweep over passes [p0, p1) (tape slot p - p0), updating the
 // adjoint state and adding this segment's gradient parts to gpart.
-template <int KP>
-__global__ __launch_bounds__(kT) void unr_reverse_kernel(UnrolledArgs a, int p0, int p1) {
-  extern __shared__ float lds[];
+template <int KP, int NT>
+__global__ __launch_bounds__(NT) void unr_reverse_kernel(UnrolledArgs a, int p0, int p1) {
+  constexpr int kT = NT;
+  extern __shared__ __attribute__((aligned(16))) float lds[];
   const int b = blockIdx.x;
   const Inst I = inst_of(a, b);
   const int T = a.T, M2 = a.M2, M2P = a.M2P, K = a.K, W = a.W;
@@ -416,8 +442,12 @@ __global__ __launch_bounds__(kT) void unr_reverse_kernel(UnrolledArgs a, int p0,
   float* om = qb + W * KP;                 // [W]
   float* zs = om + W;                      // [W + 1]
   __shared__ double dred[kT];
-  float* abar = I.adj + K * M2P;
+  // [T][KP]: in LDS when it fits (loaded here, written back at the end)
+  const bool alds = coef_in_lds(T, KP);
+  float* abar = alds ? lds + coef_lds_offset(K * M2P + 2 * W * KP + 2 * W + 1) : I.adj + K * M2P;
   const int tid = threadIdx.x;
+  if (alds)
+    for (int e = tid; e < T * KP; e += kT) abar[e] = I.adj[K * M2P + e];
   const float eps = a.theta[1], mu = a.theta[2];
   for (int s = tid; s < W; s += kT) om[s] = a.theta[3 + s];
   if (tid == 0) {
@@ -496,6 +526,8 @@ __global__ __launch_bounds__(kT) void unr_reverse_kernel(UnrolledArgs a, int p0,
     }
   }
   for (int e = tid; e < K * M2P; e += kT) I.adj[e] = wb[e];
+  if (alds)
+    for (int e = tid; e < T * KP; e += kT) I.adj[K * M2P + e] = abar[e];
   // fixed-order block sums of the scalar parts
   double* gp = I.gpart;
   const double parts[3] = {g_sig, g_eps, g_mu};
@@ -567,12 +599,13 @@ __global__ __launch_bounds__(kT) void unr_grad_kernel(UnrolledArgs a, float* gra
 template <int KP>
 hipError_t forward_k(const UnrolledArgs& a, float* loss, hipStream_t s) {
   hipLaunchKernelGGL(unr_gram_kernel, dim3((a.T + 15) / 16, (a.T + 15) / 16, a.n), dim3(kT), 0, s, a);
+  constexpr int NT = seq_threads<KP>();
   const size_t lds = unrolled_pass_lds(a);
-  auto pk = unr_pass_kernel<KP>;
+  auto pk = unr_pass_kernel<KP, NT, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pk),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pk, dim3(a.n), dim3(kT), lds, s, a, 0, a.passes, 0);
+  hipLaunchKernelGGL(pk, dim3(a.n), dim3(NT), lds, s, a, 0, a.passes);
   const dim3 gv((2 * a.S + kT - 1) / kT, a.n);
   if (a.M2 <= 16) hipLaunchKernelGGL((unr_val_fwd_kernel<KP, 16>), gv, dim3(kT), 0, s, a);
   else if (a.M2 <= 32) hipLaunchKernelGGL((unr_val_fwd_kernel<KP, 32>), gv, dim3(kT), 0, s, a);
@@ -590,10 +623,11 @@ hipError_t backward_k(const UnrolledArgs& a, float* grad, const float* upstream,
   else if (a.M2 <= 32) hipLaunchKernelGGL((unr_val_bwd_kernel<KP, 32>), gb, dim3(kT), 0, s, a);
   else if (a.M2 <= 64) hipLaunchKernelGGL((unr_val_bwd_kernel<KP, 64>), gb, dim3(kT), 0, s, a);
   else hipLaunchKernelGGL((unr_val_bwd_kernel<KP, 128>), gb, dim3(kT), 0, s, a);
+  constexpr int NT = seq_threads<KP>();
   const size_t lds_p = unrolled_pass_lds(a);
   const size_t lds_r = unrolled_reverse_lds(a);
-  auto pk = unr_pass_kernel<KP>;
-  auto rk = unr_reverse_kernel<KP>;
+  auto pk = unr_pass_kernel<KP, NT, true>;
+  auto rk = unr_reverse_kernel<KP, NT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(pk),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_p);
   if (e == hipSuccess)
@@ -604,8 +638,8 @@ hipError_t backward_k(const UnrolledArgs& a, float* grad, const float* upstream,
   for (int sgm = nseg - 1; sgm >= 0; --sgm) {
     const int p0 = sgm * a.E;
     const int p1 = p0 + a.E < a.passes ? p0 + a.E : a.passes;
-    hipLaunchKernelGGL(pk, dim3(a.n), dim3(kT), lds_p, s, a, p0, p1, 1);
-    hipLaunchKernelGGL(rk, dim3(a.n), dim3(kT), lds_r, s, a, p0, p1);
+    hipLaunchKernelGGL(pk, dim3(a.n), dim3(NT), lds_p, s, a, p0, p1);
+    hipLaunchKernelGGL(rk, dim3(a.n), dim3(NT), lds_r, s, a, p0, p1);
   }
   hipLaunchKernelGGL(unr_grad_kernel, dim3(1), dim3(kT), 0, s, a, grad, upstream);
   return hipGetLastError();
@@ -614,12 +648,15 @@ hipError_t backward_k(const UnrolledArgs& a, float* grad, const float* upstream,
 }  // namespace
 
 size_t unrolled_pass_lds(const UnrolledArgs& a) {
-  const int C = kT / a.WP;
-  return sizeof(float) * ((size_t)a.K * a.M2P + 2 * (size_t)a.WP * C * a.KP + (size_t)a.W * a.KP + 2 * a.W + 1);
+  const int nt = a.KP <= 8 ? seq_threads<8>() : seq_threads<16>();
+  const int C = nt / a.WP;
+  const size_t before = (size_t)a.K * a.M2P + 2 * (size_t)a.WP * C * a.KP + (size_t)a.W * a.KP + 2 * a.W + 1;
+  return sizeof(float) * (coef_in_lds(a.T, a.KP) ? coef_lds_offset(before) + (size_t)a.T * a.KP : before);
 }
 
 size_t unrolled_reverse_lds(const UnrolledArgs& a) {
-  return sizeof(float) * ((size_t)a.K * a.M2P + 2 * (size_t)a.W * a.KP + 2 * a.W + 1);
+  const size_t before = (size_t)a.K * a.M2P + 2 * (size_t)a.W * a.KP + 2 * a.W + 1;
+  return sizeof(float) * (coef_in_lds(a.T, a.KP) ? coef_lds_offset(before) + (size_t)a.T * a.KP : before);
 }
 
 hipError_t launch_unrolled_forward(const UnrolledArgs& a, float* loss, hipStream_t s) {
