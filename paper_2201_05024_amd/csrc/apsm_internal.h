@@ -212,7 +212,8 @@ struct UnrolledArgs {
   const float* sym_val;     // [n][S][K][2]
   void* ws;
   size_t inst_bytes;
-  size_t off_G, off_D, off_ck, off_st, off_sc, off_tx, off_th, off_adj, off_fbar, off_lpart, off_spart, off_gpart;
+  size_t off_G, off_D, off_ck, off_st, off_sc, off_tx, off_th, off_adj, off_X, off_fbar, off_lpart, off_spart,
+      off_gpart;
   int n, P, T, M2, M2P, K, KP, S, W, WP, passes, E;
   float wl, wg;
   float inv_count;          // 1 / (n * S * K)

@@ -43,12 +43,14 @@ template <int KP>
 constexpr int seq_threads() { return KP <= 8 ? 1024 : 512; }
 
 // The Gaussian coefficients (forward) or their adjoints (reverse), [T][KP],
-// are kept in LDS when they fit this budget, else in the workspace.
-constexpr size_t kCoefLdsMax = 64 * 1024;
-__host__ __device__ inline bool coef_in_lds(int T, int KP) { return (size_t)T * KP * sizeof(float) <= kCoefLdsMax; }
-// Their offset in the dynamic LDS (floats): after the other arrays, rounded
-// up to 16 bytes for the vector reads.
+// are kept in LDS after the kernel's other dynamic arrays (`before` floats,
+// the offset rounded up to 16 bytes for the vector reads) when the whole
+// fits this budget of dynamic LDS, else in the workspace.
+constexpr size_t kDynLdsFloats = 36864;      // 144 KiB
 __host__ __device__ inline size_t coef_lds_offset(size_t floats_before) { return (floats_before + 3) / 4 * 4; }
+__host__ __device__ inline bool coef_in_lds(int T, int KP, size_t before) {
+  return coef_lds_offset(before) + (size_t)T * KP <= kDynLdsFloats;
+}
 
 __device__ __forceinline__ float comp(const float* rx, int M2, int n, int m) {
   // component m of real sample n: r_{2t} = r1(t), r_{2t+1} = r2(t) = [Im; -Re]
@@ -70,7 +72,8 @@ struct Inst {
   float* sc;      // [K*M2P + T*KP]  state of the segment re-runs of the reverse sweep
   float* tx;      // [E][T][W][KP]
   float* th;      // [E][T][W][KP]
-  float* adj;     // [K*M2P + T*KP]  wbar then abar
+  float* adj;     // [K*M2P + T*KP]  wbar, then the adjoint of alpha from the validation loss
+  float* X;       // [T][KP]         step adjoints accumulated by sample (reverse sweep)
   float* fbar;    // [Sr][KP]
   float* lpart;   // [nvb]
   float* spart;   // [nib]
@@ -88,6 +91,7 @@ __device__ Inst inst_of(const UnrolledArgs& a, int b) {
   I.tx = reinterpret_cast<float*>(base + a.off_tx);
   I.th = reinterpret_cast<float*>(base + a.off_th);
   I.adj = reinterpret_cast<float*>(base + a.off_adj);
+  I.X = reinterpret_cast<float*>(base + a.off_X);
   I.fbar = reinterpret_cast<float*>(base + a.off_fbar);
   I.lpart = reinterpret_cast<float*>(base + a.off_lpart);
   I.spart = reinterpret_cast<float*>(base + a.off_spart);
@@ -125,35 +129,48 @@ __global__ __launch_bounds__(kT) void unr_gram_kernel(UnrolledArgs a) {
 
 // ---------------------------------------------------------------- passes
 // Runs passes [p0, p1) of one instance.  The state starts from zero (p0 = 0)
-// or from checkpoint p0 / E.  With tape set, x and h of every step are
-// recorded (pass p at tape slot p - p0); otherwise checkpoints are written at
-// the start of every pass p with p % E == 0.
+// or from checkpoint p0 / E.  With TAPE, x and h of every step are recorded
+// (pass p at tape slot p - p0); otherwise checkpoints are written at the
+// start of every pass p with p % E == 0.
+//
+// The window predictions are kept up to date incrementally, as in the
+// training kernel: only the member entering at step n is evaluated against
+// the whole expansion (one row of G, and of G D for the sigma sums); every
+// member's value then changes by the step's update evaluated at it, from
+// the pairwise linear products, G and D among the members (LDS rings).  Each
+// pass restarts the window, so a pass depends only on the state at its start
+// (the checkpoints), whatever the checkpoint interval.
 template <int KP, int NT, bool TAPE>
 __global__ __launch_bounds__(NT) void unr_pass_kernel(UnrolledArgs a, int p0, int p1) {
-  constexpr int kT = NT;
-  constexpr bool tape = TAPE;
+  constexpr int NWV = NT / 64;
   extern __shared__ __attribute__((aligned(16))) float lds[];
   const int b = blockIdx.x;
   const Inst I = inst_of(a, b);
-  const int T = a.T, M2 = a.M2, M2P = a.M2P, K = a.K, W = a.W;
+  const int T = a.T, M2 = a.M2, M2P = a.M2P, K = a.K, W = a.W, R = W + 1;
   const float* rx = a.rx_pilot + (size_t)b * a.P * M2;
   const float* sym = a.sym_pilot + (size_t)b * a.P * K * 2;
-  const int WP = a.WP, C = kT / WP;
   float* wl = lds;                          // [K][M2P]
-  float* part = wl + K * M2P;               // [WP][C][KP] e, then h
-  float* parth = part + WP * C * KP;
-  float* cbuf = parth + WP * C * KP;        // [W][KP]
-  float* om = cbuf + W * KP;                // [W] omega, [W + 1] prefix sums
-  float* zs = om + W;
+  float* part = wl + K * M2P;               // [NWV][KP] the entering member's prediction, per wave
+  float* parth = part + NWV * KP;           // [NWV][KP] its sigma sums
+  float* cbuf = parth + NWV * KP;           // [W][KP] coefficients of the step, by position s
+  float* ew = cbuf + W * KP;                // [W][KP] f_n(r_j) of the members, by j % W
+  float* hw = ew + W * KP;                  // [W][KP] sum_i alpha_ik G_ij D_ij, by j % W
+  float* rw = hw + W * KP;                  // [W + 1][M2P] member vectors and r_{n+1}, by j % (W + 1)
+  float* lg = rw + R * M2P;                 // [W][W] r_i . r_j of members, by (i % W, j % W)
+  float* gg = lg + W * W;                   // [W][W] G_ij
+  float* dd = gg + W * W;                   // [W][W] D_ij
+  float* om = dd + W * W;                   // [W] omega
+  float* zs = om + W;                       // [W + 1] prefix sums of omega
   const int SW = K * M2P + T * KP;
-  float* const state = tape ? I.sc : I.st;
+  float* const state = TAPE ? I.sc : I.st;
   // [T][KP]: in LDS when it fits (written back to the state at the end)
-  const bool alds = coef_in_lds(T, KP);
-  float* alpha = alds ? lds + coef_lds_offset(K * M2P + 2 * WP * C * KP + W * KP + 2 * W + 1) : state + K * M2P;
-  const int tid = threadIdx.x;
+  const size_t before = (size_t)K * M2P + 2 * NWV * KP + 3 * W * KP + (size_t)R * M2P + 3 * W * W + 2 * W + 1;
+  const bool alds = coef_in_lds(T, KP, before);
+  float* alpha = alds ? lds + coef_lds_offset(before) : state + K * M2P;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  const float sigma = a.theta[0], eps = a.theta[1], mu = a.theta[2];
-  for (int s = tid; s < W; s += kT) om[s] = a.theta[3 + s];
+  const float eps = a.theta[1], mu = a.theta[2];
+  for (int s = tid; s < W; s += NT) om[s] = a.theta[3 + s];
   if (tid == 0) {
     float z = 0.0f;
     zs[0] = 0.0f;
@@ -161,31 +178,32 @@ __global__ __launch_bounds__(NT) void unr_pass_kernel(UnrolledArgs a, int p0, in
   }
   // initial state
   const float* src = p0 == 0 ? nullptr : I.ck + (size_t)(p0 / a.E) * SW;
-  for (int e = tid; e < K * M2P; e += kT) wl[e] = src ? src[e] : 0.0f;
-  for (int e = tid; e < T * KP; e += kT) alpha[e] = src ? src[K * M2P + e] : 0.0f;
+  for (int e = tid; e < K * M2P; e += NT) wl[e] = src ? src[e] : 0.0f;
+  for (int e = tid; e < T * KP; e += NT) alpha[e] = src ? src[K * M2P + e] : 0.0f;
   __syncthreads();
-  (void)sigma;
 
-  const int my_s = tid / C, my_c = tid - (tid / C) * C;
   for (int p = p0; p < p1; ++p) {
-    if (!tape && p % a.E == 0) {
+    if (!TAPE && p % a.E == 0) {
       float* dst = I.ck + (size_t)(p / a.E) * SW;
-      for (int e = tid; e < K * M2P; e += kT) dst[e] = wl[e];
-      for (int e = tid; e < T * KP; e += kT) dst[K * M2P + e] = alpha[e];
+      for (int e = tid; e < K * M2P; e += NT) dst[e] = wl[e];
+      for (int e = tid; e < T * KP; e += NT) dst[K * M2P + e] = alpha[e];
     }
+    if (tid < M2P) rw[tid] = tid < M2 ? comp(rx, M2, 0, tid) : 0.0f;   // r_0
+    __syncthreads();
     for (int n = 0; n < T; ++n) {
       const int L = n + 1 < W ? n + 1 : W;
-      // phase 1: partial sums over dictionary entries i = c, c + C, ...
-      if (my_s < L) {
-        const int j = n - my_s;
-        const float* grow = I.G + (size_t)j * T;
-        const float* drow = I.Dm + (size_t)j * T;
+      const int jr = n % W, vr = n % R;
+      // phase 1: the entering member r_n against the expansion (per-wave sums)
+      {
         float pe[KP], ph[KP];
 #pragma unroll
         for (int k = 0; k < KP; ++k) { pe[k] = 0.0f; ph[k] = 0.0f; }
-        for (int i = my_c; i < T; i += C) {
+        const float* grow = I.G + (size_t)n * T;
+        const float* drow = I.Dm + (size_t)n * T;
+        for (int i = tid; i < T; i += NT) {
           const float g = grow[i];
           const float4* ar = reinterpret_cast<const float4*>(alpha + (size_t)i * KP);
+          const float gd = TAPE ? g * drow[i] : 0.0f;
 #pragma unroll
           for (int q = 0; q < KP / 4; ++q) {
             const float4 v = ar[q];
@@ -193,12 +211,7 @@ __global__ __launch_bounds__(NT) void unr_pass_kernel(UnrolledArgs a, int p0, in
             pe[4 * q + 1] = fmaf(v.y, g, pe[4 * q + 1]);
             pe[4 * q + 2] = fmaf(v.z, g, pe[4 * q + 2]);
             pe[4 * q + 3] = fmaf(v.w, g, pe[4 * q + 3]);
-          }
-          if constexpr (TAPE) {
-            const float gd = g * drow[i];
-#pragma unroll
-            for (int q = 0; q < KP / 4; ++q) {
-              const float4 v = ar[q];
+            if constexpr (TAPE) {
               ph[4 * q] = fmaf(v.x, gd, ph[4 * q]);
               ph[4 * q + 1] = fmaf(v.y, gd, ph[4 * q + 1]);
               ph[4 * q + 2] = fmaf(v.z, gd, ph[4 * q + 2]);
@@ -206,36 +219,67 @@ __global__ __launch_bounds__(NT) void unr_pass_kernel(UnrolledArgs a, int p0, in
             }
           }
         }
-        float* pp = part + ((size_t)my_s * C + my_c) * KP;
-        float* ppg = parth + ((size_t)my_s * C + my_c) * KP;
 #pragma unroll
-        for (int k = 0; k < KP; ++k) { pp[k] = pe[k]; ppg[k] = ph[k]; }
+        for (int k = 0; k < KP; ++k) {
+          for (int off = 32; off > 0; off >>= 1) {
+            pe[k] += __shfl_xor(pe[k], off);
+            if constexpr (TAPE) ph[k] += __shfl_xor(ph[k], off);
+          }
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int k = 0; k < KP; ++k) {
+            part[wave * KP + k] = pe[k];
+            parth[wave * KP + k] = ph[k];
+          }
+        }
+      }
+      // the entering member's pairs with the members (itself included)
+      for (int s = tid; s < L; s += NT) {
+        const int j = n - s, jm = j % W;
+        const float* r1 = rw + vr * M2P;
+        const float* r2 = rw + (j % R) * M2P;
+        float d = 0.0f;
+        for (int m = 0; m < M2; ++m) d = fmaf(r1[m], r2[m], d);
+        const float g = I.G[(size_t)n * T + j], dv = I.Dm[(size_t)n * T + j];
+        lg[jr * W + jm] = d;
+        lg[jm * W + jr] = d;
+        gg[jr * W + jm] = g;
+        gg[jm * W + jr] = g;
+        dd[jr * W + jm] = dv;
+        dd[jm * W + jr] = dv;
       }
       __syncthreads();
       // phase 2: predictions, projection coefficients, tape
       const float Z = zs[L];
-      for (int t = tid; t < L * KP; t += kT) {
+      for (int t = tid; t < L * KP; t += NT) {
         const int s = t / KP, k = t - s * KP;
         float c = 0.0f;
         if (k < K) {
-          const int j = n - s;
-          float e = 0.0f, h = 0.0f, lin = 0.0f, nrm = 0.0f;
-          for (int cc = 0; cc < C; ++cc) {
-            e += part[((size_t)s * C + cc) * KP + k];
-            h += parth[((size_t)s * C + cc) * KP + k];
+          const int j = n - s, jm = j % W;
+          float e, h;
+          if (s == 0) {
+            e = 0.0f;
+            h = 0.0f;
+            for (int w = 0; w < NWV; ++w) {
+              e += part[w * KP + k];
+              h += parth[w * KP + k];
+            }
+            float lin = 0.0f;
+            for (int m = 0; m < M2; ++m) lin = fmaf(wl[k * M2P + m], rw[vr * M2P + m], lin);
+            e += lin;
+            ew[jm * KP + k] = e;
+            hw[jm * KP + k] = h;
+          } else {
+            e = ew[jm * KP + k];
+            h = hw[jm * KP + k];
           }
-          for (int m = 0; m < M2; ++m) {
-            const float r = comp(rx, M2, j, m);
-            lin = fmaf(wl[k * M2P + m], r, lin);
-            nrm = fmaf(r, r, nrm);
-          }
-          e += lin;
           const float x = e - target(sym, K, j, k);
-          const float kjj = a.wl * nrm + a.wg;
+          const float kjj = a.wl * lg[jm * W + jm] + a.wg;
           const float mag = fabsf(x) - eps;
           const float beta = (mag > 0.0f && kjj > 0.0f) ? -copysignf(mag, x) / kjj : 0.0f;
           c = mu * (om[s] / Z) * beta;
-          if (tape) {
+          if constexpr (TAPE) {
             const size_t o = (((size_t)(p - p0) * T + n) * W + s) * KP + k;
             I.tx[o] = x;
             I.th[o] = h;
@@ -244,23 +288,38 @@ __global__ __launch_bounds__(NT) void unr_pass_kernel(UnrolledArgs a, int p0, in
         cbuf[s * KP + k] = c;
       }
       __syncthreads();
-      // phase 3: state update (every coefficient from the same f_n)
-      for (int e = tid; e < K * M2; e += kT) {
+      // phase 3: state update (every coefficient from the same f_n) and the
+      // members' running values after it (those that stay in the window)
+      for (int e = tid; e < K * M2; e += NT) {
         const int k = e / M2, m = e - k * M2;
         float acc = 0.0f;
-        for (int s = 0; s < L; ++s) acc = fmaf(cbuf[s * KP + k], comp(rx, M2, n - s, m), acc);
+        for (int s = 0; s < L; ++s) acc = fmaf(cbuf[s * KP + k], rw[((n - s) % R) * M2P + m], acc);
         wl[k * M2P + m] = fmaf(a.wl, acc, wl[k * M2P + m]);
       }
-      for (int t = tid; t < L * KP; t += kT) {
+      for (int t = tid; t < L * KP; t += NT) {
         const int s = t / KP, k = t - s * KP;
         if (k < K) alpha[(size_t)(n - s) * KP + k] = fmaf(a.wg, cbuf[s * KP + k], alpha[(size_t)(n - s) * KP + k]);
+        if (k < K && s < W - 1) {
+          const int im = (n - s) % W;
+          float de = 0.0f, dh = 0.0f;
+          for (int s2 = 0; s2 < L; ++s2) {
+            const int jm2 = (n - s2) % W;
+            const float c = cbuf[s2 * KP + k];
+            const float gv = gg[im * W + jm2];
+            de = fmaf(c, fmaf(a.wl, lg[im * W + jm2], a.wg * gv), de);
+            if constexpr (TAPE) dh = fmaf(c * a.wg, gv * dd[im * W + jm2], dh);
+          }
+          ew[im * KP + k] += de;
+          if constexpr (TAPE) hw[im * KP + k] += dh;
+        }
       }
+      if (n + 1 < T && tid < M2P) rw[((n + 1) % R) * M2P + tid] = tid < M2 ? comp(rx, M2, n + 1, tid) : 0.0f;
       __syncthreads();
     }
   }
-  for (int e = tid; e < K * M2P; e += kT) state[e] = wl[e];
+  for (int e = tid; e < K * M2P; e += NT) state[e] = wl[e];
   if (alds)
-    for (int e = tid; e < T * KP; e += kT) state[K * M2P + e] = alpha[e];
+    for (int e = tid; e < T * KP; e += NT) state[K * M2P + e] = alpha[e];
 }
 
 // ---------------------------------------------------------------- validation
@@ -428,52 +487,106 @@ __global__ __launch_bounds__(kT) void unr_val_bwd_kernel(UnrolledArgs a) {
 // ---------------------------------------------------------------- reverse
 // Reverse sweep over passes [p0, p1) (tape slot p - p0), updating the
 // adjoint state and adding this segment's gradient parts to gpart.
+//
+// The adjoint of alpha is needed only at the window members.  It is kept
+// as abar = abar0 + G X, abar0 the validation loss's part (unchanged) and
+// X_i the step adjoints xbar accumulated by sample i; a member entering the
+// window (in reverse order) is evaluated with one row of G, and the members'
+// values then change by the step's xbar through the G block among them.  X
+// carries over between segments in the workspace.
 template <int KP, int NT>
 __global__ __launch_bounds__(NT) void unr_reverse_kernel(UnrolledArgs a, int p0, int p1) {
-  constexpr int kT = NT;
+  constexpr int NWV = NT / 64;
   extern __shared__ __attribute__((aligned(16))) float lds[];
   const int b = blockIdx.x;
   const Inst I = inst_of(a, b);
   const int T = a.T, M2 = a.M2, M2P = a.M2P, K = a.K, W = a.W;
   const float* rx = a.rx_pilot + (size_t)b * a.P * M2;
   float* wb = lds;                         // [K][M2P] wbar
-  float* eb = wb + K * M2P;                // [W][KP] xbar (= ebar)
+  float* eb = wb + K * M2P;                // [W][KP] xbar (= ebar), by position s
   float* qb = eb + W * KP;                 // [W][KP] qbar parts
-  float* om = qb + W * KP;                 // [W]
+  float* abw = qb + W * KP;                // [W][KP] abar of the members, by j % W
+  float* red = abw + W * KP;               // [NWV][KP] per-wave sums of a row
+  float* rw = red + NWV * KP;              // [W + 1][M2P] member vectors, by j % (W + 1)
+  float* nw = rw + (W + 1) * M2P;          // [W + 1] their squared norms
+  float* om = nw + W + 1;                  // [W]
   float* zs = om + W;                      // [W + 1]
-  __shared__ double dred[kT];
-  // [T][KP]: in LDS when it fits (loaded here, written back at the end)
-  const bool alds = coef_in_lds(T, KP);
-  float* abar = alds ? lds + coef_lds_offset(K * M2P + 2 * W * KP + 2 * W + 1) : I.adj + K * M2P;
-  const int tid = threadIdx.x;
-  if (alds)
-    for (int e = tid; e < T * KP; e += kT) abar[e] = I.adj[K * M2P + e];
+  __shared__ double dred[NT];
+  const float* abar0 = I.adj + K * M2P;
+  // X [T][KP]: in LDS when it fits (loaded here, written back at the end)
+  const size_t before = (size_t)K * M2P + 3 * W * KP + NWV * KP + (size_t)(W + 1) * (M2P + 1) + 2 * W + 1;
+  const bool xl = coef_in_lds(T, KP, before);
+  float* X = xl ? lds + coef_lds_offset(before) : I.X;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (xl)
+    for (int e = tid; e < T * KP; e += NT) X[e] = I.X[e];
   const float eps = a.theta[1], mu = a.theta[2];
-  for (int s = tid; s < W; s += kT) om[s] = a.theta[3 + s];
+  for (int s = tid; s < W; s += NT) om[s] = a.theta[3 + s];
   if (tid == 0) {
     float z = 0.0f;
     zs[0] = 0.0f;
     for (int s = 0; s < W; ++s) { z += a.theta[3 + s]; zs[s + 1] = z; }
   }
-  for (int e = tid; e < K * M2P; e += kT) wb[e] = I.adj[e];
+  for (int e = tid; e < K * M2P; e += NT) wb[e] = I.adj[e];
   __syncthreads();
   double g_sig = 0.0, g_eps = 0.0, g_mu = 0.0, g_om = 0.0;   // g_om: lane s of wave 0
   for (int p = p1 - 1; p >= p0; --p) {
     for (int n = T - 1; n >= 0; --n) {
       const int L = n + 1 < W ? n + 1 : W;
       const float Z = zs[L];
-      for (int t = tid; t < L * KP; t += kT) {
+      // members entering the window: all of them at the pass's last step,
+      // afterwards n - W + 1 (none once the window reaches sample 0)
+      const int j_lo = n == T - 1 ? n - L + 1 : n - W + 1;
+      const int j_hi = n == T - 1 ? n : n - W + 1;
+      for (int j = j_lo < 0 ? 0 : j_lo; j <= j_hi; ++j) {
+        if (tid < M2P) rw[(j % (W + 1)) * M2P + tid] = tid < M2 ? comp(rx, M2, j, tid) : 0.0f;
+        float acc[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) acc[k] = 0.0f;
+        const float* grow = I.G + (size_t)j * T;
+        for (int i = tid; i < T; i += NT) {
+          const float g = grow[i];
+          const float4* xr = reinterpret_cast<const float4*>(X + (size_t)i * KP);
+#pragma unroll
+          for (int q = 0; q < KP / 4; ++q) {
+            const float4 v = xr[q];
+            acc[4 * q] = fmaf(v.x, g, acc[4 * q]);
+            acc[4 * q + 1] = fmaf(v.y, g, acc[4 * q + 1]);
+            acc[4 * q + 2] = fmaf(v.z, g, acc[4 * q + 2]);
+            acc[4 * q + 3] = fmaf(v.w, g, acc[4 * q + 3]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+          for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+        if (lane == 0) {
+#pragma unroll
+          for (int k = 0; k < KP; ++k) red[wave * KP + k] = acc[k];
+        }
+        __syncthreads();
+        if (tid < KP) {
+          float v = 0.0f;
+          for (int w = 0; w < NWV; ++w) v += red[w * KP + tid];
+          abw[(j % W) * KP + tid] = abar0[(size_t)j * KP + tid] + v;
+        }
+        if (tid == 64) {                   // its squared norm (wave 1; the vector was written before the barrier)
+          const float* r = rw + (j % (W + 1)) * M2P;
+          float nr = 0.0f;
+          for (int m = 0; m < M2; ++m) nr = fmaf(r[m], r[m], nr);
+          nw[j % (W + 1)] = nr;
+        }
+        __syncthreads();
+      }
+      for (int t = tid; t < L * KP; t += NT) {
         const int s = t / KP, k = t - s * KP;
         float xb = 0.0f, qp = 0.0f;
         if (k < K) {
           const int j = n - s;
-          float dot = 0.0f, nrm = 0.0f;
-          for (int m = 0; m < M2; ++m) {
-            const float r = comp(rx, M2, j, m);
-            dot = fmaf(wb[k * M2P + m], r, dot);
-            nrm = fmaf(r, r, nrm);
-          }
-          const float cb = a.wl * dot + a.wg * abar[(size_t)j * KP + k];
+          const float* r = rw + (j % (W + 1)) * M2P;
+          float dot = 0.0f;
+          for (int m = 0; m < M2; ++m) dot = fmaf(wb[k * M2P + m], r[m], dot);
+          const float nrm = nw[j % (W + 1)];
+          const float cb = a.wl * dot + a.wg * abw[(j % W) * KP + k];
           const size_t o = (((size_t)(p - p0) * T + n) * W + s) * KP + k;
           const float x = I.tx[o], h = I.th[o];
           const float kjj = a.wl * nrm + a.wg;
@@ -502,40 +615,38 @@ __global__ __launch_bounds__(NT) void unr_reverse_kernel(UnrolledArgs a, int p0,
         for (int off = 32; off > 0; off >>= 1) qq += __shfl_xor(qq, off);
         if (tid < L) g_om += (double)((qs - qq) / Z);
       }
-      for (int e = tid; e < K * M2; e += kT) {
+      for (int e = tid; e < K * M2; e += NT) {
         const int k = e / M2, m = e - k * M2;
         float acc = 0.0f;
-        for (int s = 0; s < L; ++s) acc = fmaf(eb[s * KP + k], comp(rx, M2, n - s, m), acc);
+        for (int s = 0; s < L; ++s) acc = fmaf(eb[s * KP + k], rw[((n - s) % (W + 1)) * M2P + m], acc);
         wb[k * M2P + m] += acc;
       }
-      for (int i = tid; i < T; i += kT) {
-        const float* grow = I.G + (size_t)i * T + n;      // G_{i, n - s} at grow[-s]
-        float acc[KP];
-#pragma unroll
-        for (int k = 0; k < KP; ++k) acc[k] = 0.0f;
-        for (int s = 0; s < L; ++s) {
-          const float g = grow[-s];
-#pragma unroll
-          for (int k = 0; k < KP; ++k) acc[k] = fmaf(eb[s * KP + k], g, acc[k]);
+      // the step's xbar into X; the members that stay (all but n) by the G block
+      for (int t = tid; t < L * KP; t += NT) {
+        const int s = t / KP, k = t - s * KP;
+        const int j = n - s;
+        X[(size_t)j * KP + k] += eb[s * KP + k];
+        if (s >= 1) {
+          const float* grow = I.G + (size_t)j * T + n;     // G_{j, n - s2} at grow[-s2]
+          float acc = 0.0f;
+          for (int s2 = 0; s2 < L; ++s2) acc = fmaf(eb[s2 * KP + k], grow[-s2], acc);
+          abw[(j % W) * KP + k] += acc;
         }
-        float* ar = abar + (size_t)i * KP;
-#pragma unroll
-        for (int k = 0; k < KP; ++k) ar[k] += acc[k];
       }
       __syncthreads();
     }
   }
-  for (int e = tid; e < K * M2P; e += kT) I.adj[e] = wb[e];
-  if (alds)
-    for (int e = tid; e < T * KP; e += kT) I.adj[K * M2P + e] = abar[e];
+  for (int e = tid; e < K * M2P; e += NT) I.adj[e] = wb[e];
+  if (xl)
+    for (int e = tid; e < T * KP; e += NT) I.X[e] = X[e];
   // fixed-order block sums of the scalar parts
   double* gp = I.gpart;
   const double parts[3] = {g_sig, g_eps, g_mu};
   for (int q = 0; q < 3; ++q) {
     dred[tid] = parts[q];
     __syncthreads();
-    for (int s = kT / 2; s > 0; s >>= 1) {
-      if (tid < s) dred[tid] += dred[tid + s];
+    for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
+      if (tid < s2) dred[tid] += dred[tid + s2];
       __syncthreads();
     }
     if (tid == 0) gp[q] += dred[0];
@@ -548,6 +659,7 @@ __global__ __launch_bounds__(NT) void unr_reverse_kernel(UnrolledArgs a, int p0,
 __global__ __launch_bounds__(kT) void unr_zero_gpart_kernel(UnrolledArgs a) {
   const Inst I = inst_of(a, blockIdx.x);
   for (int e = threadIdx.x; e < 4 + APSM_MAX_WINDOW; e += kT) I.gpart[e] = 0.0;
+  for (int e = threadIdx.x; e < a.T * a.KP; e += kT) I.X[e] = 0.0f;
 }
 
 __global__ __launch_bounds__(kT) void unr_loss_kernel(UnrolledArgs a, float* loss) {
@@ -648,15 +760,18 @@ hipError_t backward_k(const UnrolledArgs& a, float* grad, const float* upstream,
 }  // namespace
 
 size_t unrolled_pass_lds(const UnrolledArgs& a) {
-  const int nt = a.KP <= 8 ? seq_threads<8>() : seq_threads<16>();
-  const int C = nt / a.WP;
-  const size_t before = (size_t)a.K * a.M2P + 2 * (size_t)a.WP * C * a.KP + (size_t)a.W * a.KP + 2 * a.W + 1;
-  return sizeof(float) * (coef_in_lds(a.T, a.KP) ? coef_lds_offset(before) + (size_t)a.T * a.KP : before);
+  const int nwv = (a.KP <= 8 ? seq_threads<8>() : seq_threads<16>()) / 64;
+  const size_t W = a.W;
+  const size_t before = (size_t)a.K * a.M2P + 2 * (size_t)nwv * a.KP + 3 * W * a.KP + (W + 1) * a.M2P +
+                        3 * W * W + 2 * W + 1;
+  return sizeof(float) * (coef_in_lds(a.T, a.KP, before) ? coef_lds_offset(before) + (size_t)a.T * a.KP : before);
 }
 
 size_t unrolled_reverse_lds(const UnrolledArgs& a) {
-  const size_t before = (size_t)a.K * a.M2P + 2 * (size_t)a.W * a.KP + 2 * a.W + 1;
-  return sizeof(float) * (coef_in_lds(a.T, a.KP) ? coef_lds_offset(before) + (size_t)a.T * a.KP : before);
+  const int nwv = (a.KP <= 8 ? seq_threads<8>() : seq_threads<16>()) / 64;
+  const size_t before = (size_t)a.K * a.M2P + 3 * (size_t)a.W * a.KP + (size_t)nwv * a.KP +
+                        (size_t)(a.W + 1) * (a.M2P + 1) + 2 * a.W + 1;
+  return sizeof(float) * (coef_in_lds(a.T, a.KP, before) ? coef_lds_offset(before) + (size_t)a.T * a.KP : before);
 }
 
 hipError_t launch_unrolled_forward(const UnrolledArgs& a, float* loss, hipStream_t s) {

@@ -48,6 +48,7 @@ UnrolledArgs layout(const apsm_unrolled_t* u) {
   a.off_tx = o;    o = align256(o + (size_t)a.E * T * a.W * KP * 4);
   a.off_th = o;    o = align256(o + (size_t)a.E * T * a.W * KP * 4);
   a.off_adj = o;   o = align256(o + SW * 4);
+  a.off_X = o;     o = align256(o + T * KP * 4);
   a.off_fbar = o;  o = align256(o + Sr * KP * 4);
   a.off_lpart = o; o = align256(o + (Sr + 255) / 256 * 4);
   a.off_spart = o; o = align256(o + (T + 63) / 64 * 4);
