@@ -23,11 +23,15 @@ namespace {
 #define APSM_F16_VARIANTS(X) \
   APSM_F16_VARIANTS_M(X, 0, 16) APSM_F16_VARIANTS_M(X, 8, 32) APSM_F16_VARIANTS_M(X, 16, 64)
 
-// LDS of the largest specialisation (the 2M <= 32 ones stage 128 entries)
-constexpr int kBatchLds = tile_lds_bytes<32, 8>() > tile_lds_bytes<64, 8>() ? tile_lds_bytes<32, 8>()
-                                                                             : tile_lds_bytes<64, 8>();
-static_assert(tile_lds_bytes<64, 7>() <= kBatchLds && tile_lds_bytes<32, 7>() <= kBatchLds &&
-                  tile_lds_bytes<16, 8>() <= kBatchLds, "LDS bound");
+// LDS of the largest specialisation (the 2M <= 32 ones stage 128 entries;
+// both parts grow with K)
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kBatchStage =
+    cmax(cmax(Geo<16, 8>::STAGE_BYTES, Geo<32, 8>::STAGE_BYTES), Geo<64, 8>::STAGE_BYTES);
+constexpr int kBatchSide = cmax(cmax(side_lds_bytes<16, 8>(), side_lds_bytes<32, 8>()), side_lds_bytes<64, 8>());
+static_assert(Geo<64, 7>::STAGE_BYTES <= kBatchStage && Geo<32, 7>::STAGE_BYTES <= kBatchStage &&
+                  side_lds_bytes<64, 7>() <= kBatchSide && side_lds_bytes<32, 7>() <= kBatchSide,
+              "LDS bound");
 
 // Values every lane holds alike, moved to scalar registers so that the
 // compiler treats the control flow that depends on them (the item loop, the
@@ -64,13 +68,13 @@ __device__ __forceinline__ DetJob load_job(const DetJob* p) {
   return d;
 }
 
-__device__ __forceinline__ void run_item(const DetJob* jobs, const int2* items, int item, unsigned char* lds,
-                                         unsigned int* werr) {
+__device__ __forceinline__ void run_item(const DetJob* jobs, const int2* items, int item, unsigned char* buf0,
+                                         unsigned char* buf1, unsigned char* side, unsigned int* werr) {
   const int jx = uni(items[item].x), tile = uni(items[item].y);
   const DetJob d = load_job(jobs + jx);
   switch (d.variant) {
 #define APSM_F16_CASE(id, M2P, K) \
-  case id: detect_f16_tile<M2P, K, false>(d, d.packed, tile, lds, werr); break;
+  case id: detect_f16_tile<M2P, K, false>(d, d.packed, tile, buf0, buf1, side, werr); break;
     APSM_F16_VARIANTS(APSM_F16_CASE)
 #undef APSM_F16_CASE
     default: break;
@@ -89,15 +93,17 @@ __device__ __forceinline__ int claim(unsigned int* ctr, int* s_item) {
 
 __global__ __launch_bounds__(kThreads, 2) void detect_batch_kernel(const DetJob* jobs, const int2* items,
                                                                    int n_items, unsigned int* ctr) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[kBatchLds];
+  __shared__ __attribute__((aligned(16))) unsigned char buf0[kBatchStage];
+  __shared__ __attribute__((aligned(16))) unsigned char buf1[kBatchStage];
+  __shared__ __attribute__((aligned(16))) unsigned char side[kBatchSide];
   __shared__ unsigned int werr[8];
   __shared__ int s_item;
   if (ctr == nullptr) {
-    run_item(jobs, items, blockIdx.x, lds, werr);
+    run_item(jobs, items, blockIdx.x, buf0, buf1, side, werr);
     return;
   }
   for (int item = claim(ctr, &s_item); item < n_items; item = claim(ctr, &s_item))
-    run_item(jobs, items, item, lds, werr);
+    run_item(jobs, items, item, buf0, buf1, side, werr);
   if (threadIdx.x == 0) {
     __threadfence();
     // This workgroup's last claim precedes its count; the workgroup that

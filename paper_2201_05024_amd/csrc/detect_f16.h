@@ -140,26 +140,29 @@ __device__ __forceinline__ void stage_async(const unsigned char* packed, int cap
 // s_waitcnt vmcnt(0) with the other counters left open.
 __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// LDS bytes of one tile: two dictionary stages, the linear coefficients and
-// each wave's linear terms (32 rows x KE users).
+// LDS of one tile: two dictionary stages of STAGE_BYTES each (two distinct
+// arrays), and beside them the linear coefficients and each wave's linear
+// terms (32 rows x KE users).
 template <int M2P, int K>
-constexpr int tile_lds_bytes() {
-  return 2 * Geo<M2P, K>::STAGE_BYTES + K * M2P * 4 + kWaves * 32 * Geo<M2P, K>::KE * 4;
+constexpr int side_lds_bytes() {
+  return K * M2P * 4 + kWaves * 32 * Geo<M2P, K>::KE * 4;
 }
 
 // Detection of one tile of kWaves * 16 received vectors (vectors tile * 64 ..
 // tile * 64 + 63) by the whole workgroup.  ALLOW_PIPE: the caller has the
 // registers for the one-tile-ahead products (a function holding every
 // specialisation does not).  A is DetectArgs or DetJob (the same
-// field names); lds holds tile_lds_bytes<M2P, K>() bytes (16-byte aligned),
-// werr 8 counters.  A workgroup may run tiles back to back on the same LDS
-// when a barrier separates them.
+// field names); buf0 and buf1 are two distinct LDS arrays of at least
+// Geo<M2P, K>::STAGE_BYTES bytes, side one of side_lds_bytes<M2P, K>()
+// bytes (all 16-byte aligned), werr 8 counters.  A workgroup may run tiles
+// back to back on the same LDS when a barrier separates them.
 template <int M2P, int K, bool ALLOW_PIPE, class A>
 __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char* packed, int tile,
-                                                unsigned char* lds, unsigned int* werr) {
+                                                unsigned char* buf0, unsigned char* buf1, unsigned char* side,
+                                                unsigned int* werr) {
   using G = Geo<M2P, K>;
   constexpr int NSTEP = G::NSTEP, NB = G::NB, KE = G::KE, K4 = G::K4, CSTR = G::CSTR;
-  float* wl = reinterpret_cast<float*>(lds + 2 * G::STAGE_BYTES);
+  float* wl = reinterpret_cast<float*>(side);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -266,7 +269,7 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
     }
   };
   const int nchunks = (D + CH - 1) / CH;
-  if (nchunks > 0) stage_async<M2P, K>(packed, capp, 0, lds, wave, lane);
+  if (nchunks > 0) stage_async<M2P, K>(packed, capp, 0, buf0, wave, lane);
   stage_wait();
   __syncthreads();
 
@@ -297,10 +300,14 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
     }
     __builtin_amdgcn_wave_barrier();
   }
-  for (int c = 0; c < nchunks; ++c) {
-    // the next stage was last read in chunk c - 1, which every wave has left
-    if (c + 1 < nchunks) stage_async<M2P, K>(packed, capp, (c + 1) * CH, lds + ((c + 1) & 1) * G::STAGE_BYTES, wave, lane);
-    const unsigned char* st = lds + (c & 1) * G::STAGE_BYTES;
+  // Chunk c is read from st while chunk c + 1 is copied into nx, the other
+  // buffer (last read in chunk c - 1, which every wave has left).  The two
+  // buffers are distinct LDS arrays named statically by each chunk body
+  // (the loop below is unrolled by two), so the compiler can tell that the
+  // reads of st do not alias the copy and issues them without first waiting
+  // for it.
+  auto chunk = [&](const unsigned char* st, unsigned char* nx, int c) {
+    if (c + 1 < nchunks) stage_async<M2P, K>(packed, capp, (c + 1) * CH, nx, wave, lane);
     const _Float16* dh = reinterpret_cast<const _Float16*>(st);
     const float* co = reinterpret_cast<const float*>(st + G::A_BYTES);
     if constexpr (G::PIPE && ALLOW_PIPE) {
@@ -318,6 +325,10 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
     }
     stage_wait();
     __syncthreads();
+  };
+  for (int c = 0; c < nchunks; c += 2) {
+    chunk(buf0, buf1, c);
+    if (c + 1 < nchunks) chunk(buf1, buf0, c + 1);
   }
 
   // ---- reduce-scatter over the 32 dictionary columns of each wave half
@@ -400,9 +411,11 @@ __device__ __forceinline__ void detect_f16_tile(const A& a, const unsigned char*
 
 template <int M2P, int K>
 __global__ __launch_bounds__(kThreads, 2) void detect_f16_kernel(DetectArgs a, const unsigned char* packed) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[tile_lds_bytes<M2P, K>()];
+  __shared__ __attribute__((aligned(16))) unsigned char buf0[Geo<M2P, K>::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char buf1[Geo<M2P, K>::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char side[side_lds_bytes<M2P, K>()];
   __shared__ unsigned int werr[8];
-  detect_f16_tile<M2P, K, true>(a, packed, blockIdx.x, lds, werr);
+  detect_f16_tile<M2P, K, true>(a, packed, blockIdx.x, buf0, buf1, side, werr);
 }
 
 }  // namespace f16

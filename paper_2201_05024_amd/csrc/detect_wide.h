@@ -130,21 +130,19 @@ __device__ __forceinline__ void stage_async(const unsigned char* packed, int s, 
 // s_waitcnt vmcnt(0), other counters left open.
 __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-template <int M2P>
-constexpr int tile_lds_bytes() { return 2 * Geo<M2P>::STAGE_BYTES; }
-
 __device__ __forceinline__ floatx4 mfma(const half8& a, const half8& b, const floatx4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 // Detection of work item `item` (received vectors item * kVecPerItem / 2 ..)
 // by the whole workgroup.  A is DetectArgs or DetJob (same field names);
-// lds holds tile_lds_bytes<M2P>() bytes (16-byte aligned), werr 16
+// buf0 and buf1 are two distinct LDS arrays of Geo<M2P>::STAGE_BYTES bytes
+// each (16-byte aligned), the double buffer of dictionary stages, werr 16
 // counters.  A workgroup may run items back to back on the same LDS when a
 // barrier separates them.
 template <int M2P, class A>
 __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char* packed, int item,
-                                                 unsigned char* lds, unsigned int* werr) {
+                                                 unsigned char* buf0, unsigned char* buf1, unsigned int* werr) {
   using G = Geo<M2P>;
   constexpr int NB = G::NB, NS = kNS;
   const int tid = threadIdx.x;
@@ -216,14 +214,19 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
   }
   const float mc2 = uniform_f(-a.c2);
   const int nst = (D + kStage - 1) / kStage;
-  if (nst > 0) stage_async<M2P>(packed, 0, lds, wave, lane);
+  if (nst > 0) stage_async<M2P>(packed, 0, buf0, wave, lane);
   stage_wait();
   __syncthreads();
 
-  for (int c = 0; c < nst; ++c) {
-    // the other buffer was last read in stage c - 1, which every wave has left
-    if (c + 1 < nst) stage_async<M2P>(packed, c + 1, lds + ((c + 1) & 1) * G::STAGE_BYTES, wave, lane);
-    const unsigned char* st = lds + (c & 1) * G::STAGE_BYTES;
+  // Stage c is read from st while stage c + 1 is copied into nx, the other
+  // buffer (last read in stage c - 1, which every wave has left).  The two
+  // buffers are distinct LDS arrays and each stage body names them
+  // statically (the loop below is unrolled by two), so the compiler can tell
+  // that the reads of st do not alias the copy into nx and issues them
+  // without first waiting for the copy; with one array split in halves it
+  // waits for the whole copy before the stage's first read.
+  auto stage = [&](const unsigned char* st, unsigned char* nx, int c) {
+    if (c + 1 < nst) stage_async<M2P>(packed, c + 1, nx, wave, lane);
     // The A fragments of each (row tile, component block) group are read
     // one group ahead (two register buffers), so that the LDS latency of a
     // group is covered by the previous group's matrix instructions.
@@ -286,6 +289,10 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
     }
     stage_wait();
     __syncthreads();
+  };
+  for (int c = 0; c < nst; c += 2) {
+    stage(buf0, buf1, c);
+    if (c + 1 < nst) stage(buf1, buf0, c + 1);
   }
 
   // ---- linear part (third contraction), outputs, decisions

@@ -178,9 +178,10 @@ int pack_threads(int M2, int cap) {
 
 template <int M2P>
 __global__ __launch_bounds__(kThreads) void detect_wide_kernel(DetectArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[tile_lds_bytes<M2P>()];
+  __shared__ __attribute__((aligned(16))) unsigned char buf0[Geo<M2P>::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char buf1[Geo<M2P>::STAGE_BYTES];
   __shared__ unsigned int werr[16];
-  detect_wide_tile<M2P>(a, a.packed, blockIdx.x, lds, werr);
+  detect_wide_tile<M2P>(a, a.packed, blockIdx.x, buf0, buf1, werr);
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -234,7 +235,8 @@ constexpr int batch_waves_per_simd() { return M2P == 32 ? 4 : 2; }
 template <int M2P>
 __global__ __launch_bounds__(kThreads, batch_waves_per_simd<M2P>()) void detect_wide_batch_kernel(
     const DetJob* jobs, const int2* items, int n_items, unsigned int* ctr) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[tile_lds_bytes<M2P>()];
+  __shared__ __attribute__((aligned(16))) unsigned char buf0[Geo<M2P>::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char buf1[Geo<M2P>::STAGE_BYTES];
   __shared__ unsigned int werr[16];
   __shared__ int s_item;
   const bool persistent = ctr != nullptr;
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(kThreads, batch_waves_per_simd<M2P>()) void detect_
   while (item < n_items) {
     const int jx = uni(items[item].x), tile = uni(items[item].y);
     const DetJob d = load_job(jobs + jx);
-    detect_wide_tile<M2P>(d, d.packed, tile, lds, werr);
+    detect_wide_tile<M2P>(d, d.packed, tile, buf0, buf1, werr);
     if (!persistent) break;
     item = claim(ctr, &s_item);
   }
