@@ -75,9 +75,9 @@ MEASURED_TRAFFIC = {
     # FETCH_SIZE + WRITE_SIZE of detect_wide_batch_kernel<128> per dispatch,
     # both x1.000 by the 256 MiB copy of the same runs
     # (profiles/detect_wide_large_array_counters.md)
-    "bytes": int((60942330.2 * 1.0 + 22020096.2 * 1.0) * 1024),
-    "sources": {"paper_2201_05024_amd/csrc/detect_wide.h": "f68ab1c73f6ca1a8f7822a5c5ff976534b3ac961",
-                "paper_2201_05024_amd/csrc/detect_wide.hip": "2f0f92f25462fe0d38e2031cb2fefae3a99366b2"},
+    "bytes": int((59888786.8 * 1.0 + 19922944.2 * 1.0) * 1024),
+    "sources": {"paper_2201_05024_amd/csrc/detect_wide.h": "781676de8a55f023b72f3e52ae57ab8ba5962b91",
+                "paper_2201_05024_amd/csrc/detect_wide.hip": "8ed459dc5ba8dc9f93072750609e6a1b67afc71f"},
 }
 
 

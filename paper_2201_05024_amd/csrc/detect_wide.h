@@ -225,8 +225,21 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
   // that the reads of st do not alias the copy into nx and issues them
   // without first waiting for the copy; with one array split in halves it
   // waits for the whole copy before the stage's first read.
+  //
+  // At the widest specialisation the copy is waited for at once (before
+  // the stage's first read): a full dictionary (8192 entries, 4.85 MB
+  // packed) exceeds the 4 MB L2 of an XCD, and the workgroups of an XCD
+  // share its stages through L2 only while they walk the dictionary in
+  // step.  A workgroup that runs ahead of the others, whose copy misses to
+  // HBM, then waits for it, which keeps them in step: measured on 16
+  // detectors in one launch, 62 GB fetched from HBM against 296 GB with the
+  // copy overlapped (216 GB with the copy started halfway through the
+  // stage), for 2 % more time.  Narrower dictionaries fit L2; their copy
+  // overlaps the stage.
+  constexpr bool kCopySync = M2P == 128;
   auto stage = [&](const unsigned char* st, unsigned char* nx, int c) {
     if (c + 1 < nst) stage_async<M2P>(packed, c + 1, nx, wave, lane);
+    if (kCopySync) stage_wait();
     // The A fragments of each (row tile, component block) group are read
     // one group ahead (two register buffers), so that the LDS latency of a
     // group is covered by the previous group's matrix instructions.
