@@ -14,7 +14,8 @@ generated on the device, and resident in HBM before the timed region.
 
 Further workloads in the same JSON line: the realistic slot (4 SNR points of
 one 6-user, 16-antenna slot with 1,048,576 symbols), the batched mixed-shape
-workload (256 detectors), the differentiable unrolled training (64
+workload (256 detectors; serialized, graph replay and pipelined as the
+headline), the differentiable unrolled training (64
 instances, forward + backward), the small plain case (per-call latency) and
 the paper's own shape (detection latency, context for its Table).
 
@@ -557,7 +558,7 @@ def run_slot(args, dev, s_train, s_det):
 
 # ---------------------------------------------------- batched mixed shapes (C3)
 
-def run_batched_mixed(args, dev):
+def run_batched_mixed(args, dev, s_train, s_det):
     import torch
     import synth
     import paper_2201_05024_amd as A
@@ -567,8 +568,12 @@ def run_batched_mixed(args, dev):
     params = A.Params(eps=0.05, mu=1.0, window=32)
     items, evals, syms = [], 0, 0
     cu = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    # every detector's error counts are a view of one tensor, cleared at once
+    shapes = [synth.spec_batch_mixed(i) for i in range(n)]
+    errs_all = torch.zeros(sum(sp.K for sp, _ in shapes), dtype=torch.int64, device=dev)
+    off = 0
     for i in range(n):
-        spec, D = synth.spec_batch_mixed(i)
+        spec, D = shapes[i]
         inst = synth.make_instance(spec)
         K, M2, S = spec.K, 2 * spec.M, spec.S
         items.append(A.BatchItem(
@@ -576,7 +581,8 @@ def run_batched_mixed(args, dev):
             rx=cu(inst.rx_data), modulation=spec.modulation,
             soft=torch.empty((S, K, 2), dtype=torch.float32, device=dev),
             hard=torch.empty((S, K), dtype=torch.uint8, device=dev), truth=cu(inst.truth),
-            errors=torch.zeros(K, dtype=torch.int64, device=dev), sigma2=0.5))
+            errors=errs_all[off:off + K], sigma2=0.5))
+        off += K
         evals += 2 * S * D
         syms += S * K
     batch = A.Batch(params, items)
@@ -586,8 +592,7 @@ def run_batched_mixed(args, dev):
     torch.cuda.synchronize()
 
     def batched_step():
-        for it in items:
-            it.errors.zero_()
+        errs_all.zero_()
         batch.train(stream).detect(stream)
 
     def timed(fn, steps):
@@ -605,8 +610,7 @@ def run_batched_mixed(args, dev):
     side.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=side):
-        for it in items:
-            it.errors.zero_()
+        errs_all.zero_()
         batch.train(side).detect(side)
     torch.cuda.synchronize()
     t_graph = timed(g.replay, 5)
@@ -623,11 +627,65 @@ def run_batched_mixed(args, dev):
     e[1].record(stream)
     torch.cuda.synchronize()
     det_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+
+    # Pipelined as the headline: a second model set detecting into the same
+    # outputs; the kernel rows of step k and the detection of step k - 1 on
+    # one stream, the training of step k on the other.  Plain-form detection,
+    # so the trainings get CUs as detection workgroups retire.
+    items2 = [A.BatchItem(model=A.Model(it.model.M2, it.model.K, it.model.dict_cap, dev, 0.5),
+                          rx_pilot=it.rx_pilot, sym_pilot=it.sym_pilot, rx=it.rx, modulation=it.modulation,
+                          soft=it.soft, hard=it.hard, truth=it.truth, errors=it.errors, sigma2=0.5)
+              for it in items]
+    sets = [batch, A.Batch(params, items2)]
+    for b in sets:
+        b.set_form(False)
+    trained = [torch.cuda.Event(), torch.cuda.Event()]
+    detected = [torch.cuda.Event(), torch.cuda.Event()]
+    rows_ready = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def pipelined_step(k):
+        cur, prev = k % 2, (k + 1) % 2
+        with torch.cuda.stream(s_det):
+            sets[cur].kernel_rows(s_det)
+            rows_ready[cur].record(s_det)
+        with torch.cuda.stream(s_train):
+            s_train.wait_event(detected[cur])
+            s_train.wait_event(rows_ready[cur])
+            sets[cur].train_prepared(s_train)
+            trained[cur].record(s_train)
+        with torch.cuda.stream(s_det):
+            s_det.wait_event(trained[prev])
+            errs_all.zero_()
+            sets[prev].detect(s_det)
+            detected[prev].record(s_det)
+
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s_train):
+        sets[1].train(s_train)
+        trained[1].record(s_train)
+    with torch.cuda.stream(s_det):
+        detected[0].record(s_det)
+    for k in range(2):
+        pipelined_step(k)
+    torch.cuda.synchronize()
+    steps = max(args.steps, 5)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        pipelined_step(k)
+    torch.cuda.synchronize()
+    t_pipe = (time.perf_counter() - t0) / steps
+    for b in sets[1:]:
+        b.close()
+
     out = {
         "workload": (f"{n} detectors, K 2..8, 8/16/32 antennas, dictionaries 64..2048 (= pilots), "
                      "65536 vectors each, QPSK/16-QAM mixed, SNR 5..20 dB, W=32, sigma2=0.5"),
         "batched_user_symbols_per_s": syms / t_batched,
         "ms_per_step_batched": t_batched * 1e3,
+        "pipelined_user_symbols_per_s": syms / t_pipe,
+        "ms_per_step_pipelined": t_pipe * 1e3,
+        "schedule_pipelined": ("training of step k (kernel rows, then one training launch) beside the "
+                               "plain-form detection of step k - 1 on a second stream, two model sets"),
         "graph_replay_ms": t_graph * 1e3,
         "train_ms_one_batch": e[0].elapsed_time(e[1]),
         "detect_ms_one_batch": det_s * 1e3,
@@ -640,8 +698,8 @@ def run_batched_mixed(args, dev):
                          errors=it.errors, stream=stream)
 
         def plain_step():
+            errs_all.zero_()
             for it in items:
-                it.errors.zero_()
                 p = A.Params(sigma2=0.5, eps=0.05, mu=1.0, window=32, dict_cap=it.model.dict_cap)
                 A.train(it.rx_pilot, it.sym_pilot, p, model=it.model, stream=stream)
             plain_detect()
@@ -651,6 +709,7 @@ def run_batched_mixed(args, dev):
             "plain_user_symbols_per_s": syms / t_plain,
             "ms_per_step_plain": t_plain * 1e3,
             "speedup_vs_plain": t_plain / t_batched,
+            "pipelined_speedup_vs_plain": t_plain / t_pipe,
             "detect_ms_plain": t_plain_det * 1e3,
             "detect_speedup_vs_plain": t_plain_det / det_s,
         })
@@ -790,7 +849,7 @@ def main():
     if "slot" in extra:
         out["slot"] = run_slot(args, dev, s_train, s_det)
     if "mixed" in extra:
-        out["batched_mixed"] = run_batched_mixed(args, dev)
+        out["batched_mixed"] = run_batched_mixed(args, dev, s_train, s_det)
     if "unrolled" in extra:
         out["unrolled"] = run_unrolled(dev)
     if "small" in extra:
