@@ -76,8 +76,8 @@ MEASURED_TRAFFIC = {
     # FETCH_SIZE + WRITE_SIZE of detect_wide_batch_kernel<128> per dispatch,
     # both x1.000 by the 256 MiB copy of the same runs
     # (profiles/detect_wide_large_array_counters.md)
-    "bytes": int((59888786.8 * 1.0 + 19922944.2 * 1.0) * 1024),
-    "sources": {"paper_2201_05024_amd/csrc/detect_wide.h": "781676de8a55f023b72f3e52ae57ab8ba5962b91",
+    "bytes": int((57266160.2 * 1.0 + 14680064.2 * 1.0) * 1024),
+    "sources": {"paper_2201_05024_amd/csrc/detect_wide.h": "c4466cec43db01aaded2f9d1e5d12b7c8ce86ff1",
                 "paper_2201_05024_amd/csrc/detect_wide.hip": "8ed459dc5ba8dc9f93072750609e6a1b67afc71f"},
 }
 

@@ -319,6 +319,11 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
   const float sa = ldexpf(1.0f, -e_a);
   const int bits = a.modulation >> 1;              // per axis: 1 (QPSK) or 2 (16-QAM)
   const bool has_err = __builtin_amdgcn_readfirstlane((int)(a.err != nullptr)) != 0;
+  // vector stores of the outputs: rows of 2K floats (K even) from a 16-byte
+  // aligned base start 16-byte aligned; rows of K labels (K a multiple of 4)
+  // from a 4-byte aligned base start 4-byte aligned
+  const bool vec_soft = (K % 2 == 0) && (reinterpret_cast<uintptr_t>(a.soft) & 15) == 0;
+  const bool vec_hard = (K % 4 == 0) && (reinterpret_cast<uintptr_t>(a.hard) & 3) == 0;
 #pragma unroll
   for (int t = 0; t < NS; ++t) {
     floatx4 accl = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -332,13 +337,15 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
     const int v = ((item * kWaves + wave) * NS + t) * 16 + col;
     const int smp = v >> 1, part = v & 1;
     const bool valid = smp < a.S;
+    float vals[4];
+    unsigned int labels = 0;                     // users 4g .. 4g + 3, one byte each
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 4 * g + i;
       const bool kval = k < K;
       const float val = fmaf(accl[i], sl, (acc2[t][i] + acc2x[t][i]) * sa);
+      vals[i] = val;
       bad |= valid && kval && !__builtin_isfinite(val);
-      if (a.soft && valid && kval) a.soft[((size_t)smp * K + k) * 2 + part] = val;
       if (a.modulation) {
         int idx;
         if (bits == 1) {
@@ -350,10 +357,40 @@ __device__ __forceinline__ void detect_wide_tile(const A& a, const unsigned char
         const int gr = idx ^ (idx >> 1);
         const int other = __shfl_xor(gr, 1);       // the lane holding the other part of this sample
         const int label = part == 0 ? ((gr << bits) | other) : ((other << bits) | gr);
-        if (part == 0 && valid && kval) {
-          if (a.hard) a.hard[(size_t)smp * K + k] = (uint8_t)label;
-          if (has_err && label != a.truth[(size_t)smp * K + k]) atomicAdd(&werr[k], 1u);
+        labels |= (unsigned int)(label & 0xff) << (8 * i);
+        if (part == 0 && valid && kval && has_err && label != a.truth[(size_t)smp * K + k])
+          atomicAdd(&werr[k], 1u);
+      }
+    }
+    // Soft outputs: lanes col and col ^ 1 hold the two parts of a sample, so
+    // each writes two users x two parts, 16 contiguous bytes (one store
+    // where the row offsets allow it); together the eight lanes of a sample
+    // cover its row.
+    if (a.soft) {
+      float oth[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) oth[i] = __shfl_xor(vals[i], 1);
+      const int kb = 4 * g + 2 * part;
+      const float q0 = part ? oth[2] : vals[0], q1 = part ? vals[2] : oth[0];
+      const float q2 = part ? oth[3] : vals[1], q3 = part ? vals[3] : oth[1];
+      if (valid) {
+        float* dst = a.soft + ((size_t)smp * K + kb) * 2;
+        if (vec_soft && kb + 1 < K) {
+          *reinterpret_cast<floatx4*>(dst) = floatx4{q0, q1, q2, q3};
+        } else {
+          if (kb < K) { dst[0] = q0; dst[1] = q1; }
+          if (kb + 1 < K) { dst[2] = q2; dst[3] = q3; }
         }
+      }
+    }
+    if (a.modulation && a.hard && part == 0 && valid) {
+      uint8_t* hd = a.hard + (size_t)smp * K + 4 * g;
+      if (vec_hard && 4 * g + 3 < K) {
+        *reinterpret_cast<unsigned int*>(hd) = labels;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < K) hd[i] = (uint8_t)(labels >> (8 * i));
       }
     }
   }
